@@ -1,0 +1,312 @@
+/*
+ * THIIM reference oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously-correct FP64 CPU implementation of the iterated
+ * split-field Yee update of the Time Harmonic Inverse Iteration Method
+ * (Malas et al., "Optimization of an electromagnetics code with multicore
+ * wavefront diamond blocking and multi-dimensional intra-tile
+ * parallelization", arXiv:1510.05218).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no source with the GPU library.
+ *
+ * What it follows:
+ *   - Sec. I-A, Eq. (3) and (4): leapfrog pseudo-time update with the phase
+ *     factors exp(i w tau) and exp(i w tau / 2); H^{n+1/2} uses E^n, E^{n+1}
+ *     uses H^{n+1/2}.
+ *   - Sec. I-A, Eq. (5): "back iteration" for cells with negative
+ *     permittivity (only the E coefficients change).
+ *   - Sec. I-A, Eq. (6) and (7): Berenger split field, 12 split components.
+ *   - Sec. III, Listings 1 and 2: per-component loop nest over k, j, i, the
+ *     interleaved (re, im) layout with x fastest, and the operation order of
+ *     the complex update (22 flops with a source array, 20 without).
+ *   - Sec. II-B / Fig. 3: H depends on E at an offset of -1, E depends on H
+ *     in the opposite (+1) direction.
+ *
+ * Readings taken where the paper is silent (each is listed in the design
+ * notes of the repository):
+ *   - Normalised units eps0 = mu0 = c0 = 1, mu_r = 1, grid step h.
+ *   - Complex relative permittivity eps_r = eps' - i eps'' (paper's
+ *     exp(+i w tau) convention); the loss enters as sigma_mat = w eps''.
+ *   - The PML conductivity profiles (electric, per E plane; magnetic, per H
+ *     plane) are inputs; they act only on the four z-difference components.
+ *   - Ghost values beyond the z walls are zero (homogeneous Dirichlet);
+ *     x and y are periodic or Dirichlet.
+ *   - Source arrays exist only for the four z-difference components, as in
+ *     the paper's array inventory.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NCOMP 12
+#define NCOEF 28
+
+/* Split components, listing naming: F_ab is the part of field F, component a,
+ * driven by the other field's component b.  Index order (also the order of
+ * field arrays across the API):
+ *   0 H_xy  1 H_xz  2 H_yx  3 H_yz  4 H_zx  5 H_zy
+ *   6 E_xy  7 E_xz  8 E_yx  9 E_yz 10 E_zx 11 E_zy
+ *
+ * For each: the two split arrays forming the driving component G_b, the axis
+ * of the difference (0 = x, 1 = y, 2 = z) and the sign of that derivative in
+ * the curl of Eq. (1)/(2):
+ *   dH/dt = -curl E :  H_x <- +d_z E_y - d_y E_z,  H_y <- -d_z E_x + d_x E_z,
+ *                      H_z <- -d_x E_y + d_y E_x
+ *   dE/dt = +curl H :  E_x <- +d_y H_z - d_z H_y,  E_y <- +d_z H_x - d_x H_z,
+ *                      E_z <- +d_x H_y - d_y H_x
+ */
+typedef struct {
+    int g1, g2;  /* indices of the two split parts of the driving component */
+    int axis;    /* 0 x, 1 y, 2 z */
+    int sign;    /* +1 / -1 */
+    int src;     /* index of the source array (0..3) or -1 */
+} comp_t;
+
+static const comp_t COMP[NCOMP] = {
+    /* H_xy */ { 8,  9, 2, +1,  0},   /* E_y = E_yx + E_yz */
+    /* H_xz */ {10, 11, 1, -1, -1},   /* E_z = E_zx + E_zy */
+    /* H_yx */ { 6,  7, 2, -1,  1},   /* E_x = E_xy + E_xz (Listing 1) */
+    /* H_yz */ {10, 11, 0, +1, -1},
+    /* H_zx */ { 6,  7, 1, +1, -1},   /* Listing 2 */
+    /* H_zy */ { 8,  9, 0, -1, -1},
+    /* E_xy */ { 2,  3, 2, -1,  2},   /* H_y = H_yx + H_yz */
+    /* E_xz */ { 4,  5, 1, +1, -1},   /* H_z = H_zx + H_zy */
+    /* E_yx */ { 0,  1, 2, +1,  3},   /* H_x = H_xy + H_xz */
+    /* E_yz */ { 4,  5, 0, -1, -1},
+    /* E_zx */ { 0,  1, 1, -1, -1},
+    /* E_zy */ { 2,  3, 0, +1, -1},
+};
+
+/* Coefficient array order: t_q = q, c_q = 12 + q (q = 0..11),
+ * Src for H_xy, H_yx, E_xy, E_yx = 24..27.  Source input order:
+ * S_Hx, S_Hy, S_Ex, S_Ey (the field component each source drives). */
+
+typedef struct {
+    int nx, ny, nz;
+    int bcx, bcy; /* 0 periodic, 1 Dirichlet */
+} grid_t;
+
+/* Index of the neighbour of (k, j, i) one step along `axis` in direction
+ * `dir` (+1 / -1), or -1 when it lies outside the domain (ghost value 0). */
+static long nbr(const grid_t *g, int k, int j, int i, int axis, int dir)
+{
+    if (axis == 0) {
+        i += dir;
+        if (i < 0 || i >= g->nx) {
+            if (g->bcx) return -1;
+            i = (i + g->nx) % g->nx;
+        }
+    } else if (axis == 1) {
+        j += dir;
+        if (j < 0 || j >= g->ny) {
+            if (g->bcy) return -1;
+            j = (j + g->ny) % g->ny;
+        }
+    } else {
+        k += dir;
+        if (k < 0 || k >= g->nz) return -1;
+    }
+    return ((long)k * g->ny + j) * g->nx + i;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Coefficients (Eq. 3, 4, 5 solved for the new value).                    */
+/* ---------------------------------------------------------------------- */
+
+/* H update, Eq. (4) with mu = 1:
+ *   (e^{iwt/2} H^{n+1/2} - e^{-iwt/2} H^{n-1/2}) / tau
+ *       = -(curl E^n) - sigma* H^{n+1/2} + S_H
+ *   => H^{n+1/2} = t H^{n-1/2} + s c dE + Src, d = e^{iwt/2} + tau sigma*,
+ *      t = e^{-iwt/2} / d,  c = (tau / h) / d,  Src = tau S_H / d. */
+static void coef_h(double omega, double tau, double h, double sig_star,
+                   double complex *t, double complex *c, double complex *sscale)
+{
+    double complex ph2 = cexp(I * (omega * tau / 2.0));
+    double complex d = ph2 + tau * sig_star;
+    *t = conj(ph2) / d;
+    *c = (tau / h) / d;
+    *sscale = tau / d;
+}
+
+/* E update.  Forward iteration, Eq. (3), for eps' > 0:
+ *   (e^{iwt} E^{n+1} - E^n) / tau
+ *       = (1/eps) curl H e^{iwt/2} - (sigma/eps) E^{n+1} e^{iwt} + S_E
+ *   => d = 1 + tau sigma / eps,  t = e^{-iwt} / d,
+ *      c = (tau / (eps h)) e^{-iwt/2} / d,  Src = tau e^{-iwt} S_E / d.
+ * Back iteration, Eq. (5), for eps' < 0:
+ *   (e^{iwt} E^n - E^{n+1}) / tau
+ *       = (1/eps) curl H e^{iwt/2} - (sigma/eps) E^{n+1} + S_E
+ *   => d = 1 - tau sigma / eps,  t = e^{iwt} / d,
+ *      c = -(tau / (eps h)) e^{iwt/2} / d,  Src = -tau S_E / d. */
+static void coef_e(double omega, double tau, double h, double eps, double sigma,
+                   double complex *t, double complex *c, double complex *sscale)
+{
+    double complex ph = cexp(I * (omega * tau));
+    double complex ph2 = cexp(I * (omega * tau / 2.0));
+    if (eps > 0.0) {
+        double d = 1.0 + tau * sigma / eps;
+        *t = conj(ph) / d;
+        *c = (tau / (eps * h)) * conj(ph2) / d;
+        *sscale = tau * conj(ph) / d;
+    } else {
+        double d = 1.0 - tau * sigma / eps;
+        *t = ph / d;
+        *c = -(tau / (eps * h)) * ph2 / d;
+        *sscale = -tau / d;
+    }
+}
+
+static void put(double *a, long p, double complex v)
+{
+    a[2 * p] = creal(v);
+    a[2 * p + 1] = cimag(v);
+}
+
+/* Builds the 28 coefficient arrays (interleaved complex, [nz][ny][nx]).
+ *   eps   : 2*N doubles, (eps', eps'') per cell, eps_r = eps' - i eps''
+ *   sig_e : nz, electric PML conductivity at the E planes
+ *   sig_h : nz, magnetic PML conductivity at the H planes
+ *   src   : 4 pointers (S_Hx, S_Hy, S_Ex, S_Ey), 2*N doubles each, or NULL
+ * Returns 0, or -1 on eps' == 0 / non-finite input. */
+int oracle_coeffs(int nx, int ny, int nz, const double *eps,
+                  const double *sig_e, const double *sig_h,
+                  const double *const *src, double omega, double tau, double h,
+                  double *const *coef)
+{
+    long N = (long)nx * ny * nz;
+    for (long p = 0; p < N; p++) {
+        double ep = eps[2 * p], epp = eps[2 * p + 1];
+        if (!(ep != 0.0) || !isfinite(ep) || !isfinite(epp)) return -1;
+    }
+    for (int k = 0; k < nz; k++) {
+        for (int j = 0; j < ny; j++) {
+            for (int i = 0; i < nx; i++) {
+                long p = ((long)k * ny + j) * nx + i;
+                double ep = eps[2 * p], epp = eps[2 * p + 1];
+                double sig_mat = omega * epp;
+                for (int q = 0; q < NCOMP; q++) {
+                    const comp_t *cq = &COMP[q];
+                    double complex t, c, s;
+                    if (q < 6) {
+                        double sst = (cq->axis == 2) ? sig_h[k] : 0.0;
+                        coef_h(omega, tau, h, sst, &t, &c, &s);
+                    } else {
+                        double sg = sig_mat + ((cq->axis == 2) ? sig_e[k] : 0.0);
+                        coef_e(omega, tau, h, ep, sg, &t, &c, &s);
+                    }
+                    put(coef[q], p, t);
+                    put(coef[12 + q], p, c);
+                    if (cq->src >= 0) {
+                        double complex S = 0.0;
+                        const double *sa = src ? src[cq->src] : NULL;
+                        if (sa) S = sa[2 * p] + I * sa[2 * p + 1];
+                        put(coef[24 + cq->src], p, s * S);
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The 12 loop nests (Listings 1 and 2).                                   */
+/* ---------------------------------------------------------------------- */
+
+/* One component update over the whole domain, in the form of Listings 1/2:
+ *   D  = G(a) - G(b) summed part by part, (a, b) chosen so that the update
+ *        reads  F <- t F + Src - c D  (the listing always subtracts c D),
+ *   H: backward difference, E: forward difference along the component axis.
+ * With s the curl sign:  s c (G(p) - G(p-e)) = -c D  =>  D = -s (G(p) - G(p-e))
+ * for H, and D = -s (G(p+e) - G(p)) for E. */
+static void update_component(const grid_t *g, int q, double *F,
+                             const double *tq, const double *cq,
+                             const double *srcq, const double *G1,
+                             const double *G2)
+{
+    const comp_t *cm = &COMP[q];
+    const int is_h = q < 6;
+    const int dir = is_h ? -1 : +1;
+    int k;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < g->nz; k++) {
+        for (int j = 0; j < g->ny; j++) {
+            for (int ii = 0; ii < g->nx; ii++) {
+                long p = ((long)k * g->ny + j) * g->nx + ii;
+                long ps = nbr(g, k, j, ii, cm->axis, dir);
+                double g1p = G1[2 * p], g1pi = G1[2 * p + 1];
+                double g2p = G2[2 * p], g2pi = G2[2 * p + 1];
+                double g1s = 0.0, g1si = 0.0, g2s = 0.0, g2si = 0.0;
+                if (ps >= 0) {
+                    g1s = G1[2 * ps]; g1si = G1[2 * ps + 1];
+                    g2s = G2[2 * ps]; g2si = G2[2 * ps + 1];
+                }
+                /* operands (a, b) of D = G(a) - G(b) */
+                double a1, a1i, b1, b1i, a2, a2i, b2, b2i;
+                int pos_first; /* D = G(p) - G(shift) ? */
+                if (is_h) pos_first = (cm->sign < 0);  /* H: D = -s (G(p) - G(p-e)) */
+                else      pos_first = (cm->sign > 0);  /* E: D = -s (G(p+e) - G(p)) */
+                if (pos_first) {
+                    a1 = g1p; a1i = g1pi; b1 = g1s; b1i = g1si;
+                    a2 = g2p; a2i = g2pi; b2 = g2s; b2i = g2si;
+                } else {
+                    a1 = g1s; a1i = g1si; b1 = g1p; b1i = g1pi;
+                    a2 = g2s; a2i = g2si; b2 = g2p; b2i = g2pi;
+                }
+                double Re = a1 - b1 + a2 - b2;
+                double Im = a1i - b1i + a2i - b2i;
+                double fr = F[2 * p], fi = F[2 * p + 1];
+                double tr = tq[2 * p], ti = tq[2 * p + 1];
+                double cr = cq[2 * p], ci = cq[2 * p + 1];
+                double t;
+                if (srcq) {
+                    t = fr * tr - fi * ti + srcq[2 * p] - cr * Re + ci * Im;
+                    F[2 * p + 1] = fr * ti + fi * tr + srcq[2 * p + 1] - cr * Im - ci * Re;
+                } else {
+                    t = fr * tr - fi * ti - cr * Re + ci * Im;
+                    F[2 * p + 1] = fr * ti + fi * tr - cr * Im - ci * Re;
+                }
+                F[2 * p] = t;
+            }
+        }
+    }
+}
+
+/* n THIIM iterations in place: each is the H half-step (6 loop nests, Eq. 4)
+ * followed by the E half-step (6 loop nests, Eq. 3/5). */
+int oracle_iterate(int nx, int ny, int nz, int bcx, int bcy,
+                   const double *const *coef, double *const *F, int n)
+{
+    grid_t g = {nx, ny, nz, bcx, bcy};
+    for (int it = 0; it < n; it++) {
+        for (int half = 0; half < 2; half++) {
+            for (int q = 6 * half; q < 6 * half + 6; q++) {
+                const comp_t *cm = &COMP[q];
+                const double *srcq = cm->src >= 0 ? coef[24 + cm->src] : NULL;
+                update_component(&g, q, F[q], coef[q], coef[12 + q], srcq,
+                                 F[cm->g1], F[cm->g2]);
+            }
+        }
+    }
+    return 0;
+}
+
+/* Flop count of one component update, as written above (Listings 1/2). */
+int oracle_flops_per_update(int has_src) { return has_src ? 22 : 20; }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,301 @@
+"""Pins of the CPU oracle against facts other than itself (no GPU needed).
+
+Each test checks the oracle against something it does not contain:
+  * the fixed-point system written out independently from Eq. (3)-(5)
+    (``oracle.dense``) -- the exact identity Phi(x*) = x*;
+  * the textbook Yee numerical dispersion relation (closed form);
+  * the printed loop nests of Listings 1 and 2 (operation order, bitwise);
+  * structural invariants: linearity in the source, zero source, x/y
+    invariance of a flat stack, mirror symmetry x <-> y;
+  * closed forms of the coefficients for sigma = 0.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_1510_05218_amd import inputs
+
+P = oracle.physical
+
+
+def _coef(pb):
+    return oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+# --------------------------------------------------------------------------
+# Fixed point (Sec. I-A, Eq. 3-5 with E^{n+1} = E^n, H^{n+1/2} = H^{n-1/2})
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,bcx,bcy,back", [(1, 0, 0, False), (2, 1, 0, True),
+                                               (3, 0, 1, True), (4, 1, 1, False)])
+def test_fixed_point_identity(oracle_lib, seed, bcx, bcy, back):
+    """One oracle iteration leaves the directly solved fixed point unchanged,
+    for random per-cell materials, random sources on all four source arrays,
+    a graded PML and (optionally) back-iteration cells with eps' < 0."""
+    pb = inputs.random_problem(5, 4, 9, seed=seed, bcx=bcx, bcy=bcy)
+    if back:
+        g = inputs.rng(seed + 100)
+        mask = g.random(pb.eps.shape) < 0.15
+        pb.eps[mask] = -g.uniform(1, 5, mask.sum()) + 1j * g.uniform(0.1, 1, mask.sum())
+    coef = _coef(pb)
+    xs = dense.fixed_point(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega,
+                           pb.tau, pb.h, bcx, bcy)
+    y = oracle.phi(coef, xs, bcx, bcy)
+    for q in range(12):
+        assert _rel(y[q], xs[q]) < 1e-13 or np.linalg.norm(y[q] - xs[q]) < 1e-13 * np.linalg.norm(xs)
+    assert _rel(y, xs) < 1e-14
+
+
+def test_fixed_point_detects_wrong_sign(oracle_lib):
+    """The identity is sensitive: a dense system with one curl sign flipped
+    is not a fixed point of the oracle."""
+    pb = inputs.random_problem(4, 4, 8, seed=7)
+    coef = _coef(pb)
+    orig = dense.split_table
+
+    def flipped():
+        t = orig()
+        t[3] = dict(t[3], sign=-t[3]["sign"])
+        return t
+
+    dense.split_table = flipped
+    try:
+        xs = dense.fixed_point(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
+    finally:
+        dense.split_table = orig
+    assert _rel(oracle.phi(coef, xs), xs) > 1e-3
+
+
+def test_iteration_converges_to_fixed_point(oracle_lib):
+    """From x0 = 0 the iterates approach the direct solution (physical
+    fields) on a lossy textured stack with PML; the residual falls with them."""
+    pb = inputs.solar_cell(6, 6, 18, seed=1, npml=6, eps_range=(1.0, 2.0),
+                           loss_range=(0.2, 0.5), texture_amp=1)
+    pb.omega = 1.0
+    coef = _coef(pb)
+    xs = dense.fixed_point(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
+    x = oracle.zero_fields(pb.shape)
+    errs, res = [], []
+    for _ in range(5):
+        oracle.iterate(coef, x, 2000)
+        errs.append(_rel(P(x), P(xs)))
+        res.append(oracle.residual(coef, x))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert all(b < a for a, b in zip(res, res[1:]))
+    assert errs[-1] < 1e-6
+    assert oracle.residual(coef, xs) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Textbook Yee numerical dispersion
+# --------------------------------------------------------------------------
+def _yee_kz(eps, omega, tau, kt):
+    """sin^2(kz h/2) = eps sin^2(w tau/2)/tau^2 - sin^2(kt h/2), h = 1, with the
+    branch of a wave travelling (or decaying) towards +z: exp(-i kz z)."""
+    s2 = eps * np.sin(omega * tau / 2) ** 2 / tau ** 2 - np.sin(kt / 2) ** 2
+    kz = 2 * np.arcsin(np.sqrt(complex(s2)))
+    if kz.imag > 0:
+        kz = np.conj(kz)
+    return kz
+
+
+@pytest.mark.parametrize("kind,pol,axis", [("E", "y", "x"), ("H", "y", "x"),
+                                           ("E", "x", "y"), ("H", "x", "y")])
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_yee_dispersion(oracle_lib, kind, pol, axis, m):
+    """In a uniform lossless medium the fixed point is a discrete plane wave
+    whose z wave number obeys the textbook Yee dispersion relation at the
+    lateral wave number 2 pi m / n (TE and TM, along x and y; m = 2 is
+    evanescent).  Sources are divergence-free so no static charge remains."""
+    eps, n, nz, npml, omega, tau = 2.0, 16, 140, 24, 0.5, 0.5
+    nx, ny = (n, 2) if axis == "x" else (2, n)
+    e = np.full((nz, ny, nx), eps + 0j)
+    sig_e, sig_h = inputs.pml_profiles(nz, npml, npml, eps, eps)
+    src = inputs.plane_source(e.shape, npml + 5, pol=pol,
+                              kx=m if axis == "x" else 0,
+                              ky=m if axis == "y" else 0, field_kind=kind)
+    xs = dense.fixed_point(e, sig_e, sig_h, src, omega, tau)
+    coef = oracle.coeffs(e, sig_e, sig_h, src, omega, tau)
+    assert _rel(oracle.phi(coef, xs), xs) < 1e-13
+    ph = P(xs)
+    comp = ph[np.argmax([np.linalg.norm(c) for c in ph])]
+    col = comp[:, 0, 0]
+    k_s = npml + 5
+    ks = np.arange(k_s + 3, k_s + (15 if m == 2 else 60))
+    ratio = col[ks + 1] / col[ks]
+    kz = np.mean(1j * np.log(ratio))
+    pred = _yee_kz(eps, omega, tau, 2 * np.pi * m / n)
+    assert abs(kz - pred) < 2e-5 * abs(pred)
+
+
+# --------------------------------------------------------------------------
+# Listings 1 and 2 (operation order, bitwise)
+# --------------------------------------------------------------------------
+def _listing_update(F, t, c, src, g1, g2, a_shift, b_shift):
+    """Literal form of Listings 1/2 in numpy (no FMA): D = G1(a) - G1(b) +
+    G2(a) - G2(b) evaluated left to right, then t F + Src - c D."""
+    Re = g1[a_shift].real - g1[b_shift].real + g2[a_shift].real - g2[b_shift].real
+    Im = g1[a_shift].imag - g1[b_shift].imag + g2[a_shift].imag - g2[b_shift].imag
+    fr, fi = F.real, F.imag
+    if src is not None:
+        tt = fr * t.real - fi * t.imag + src.real - c.real * Re + c.imag * Im
+        im = fr * t.imag + fi * t.real + src.imag - c.real * Im - c.imag * Re
+    else:
+        tt = fr * t.real - fi * t.imag - c.real * Re + c.imag * Im
+        im = fr * t.imag + fi * t.real - c.real * Im - c.imag * Re
+    return tt + 1j * im
+
+
+def test_listing1_and_listing2_bitwise(oracle_lib):
+    g = inputs.rng(11)
+    nz, ny, nx = 5, 6, 7
+
+    def crand(*s):
+        return g.standard_normal(s) + 1j * g.standard_normal(s)
+
+    coef = crand(28, nz, ny, nx)
+    x0 = crand(12, nz, ny, nx)
+    x1 = oracle.iterate(coef, x0.copy(), 1)
+    inner = (slice(None),) * 3
+    # Listing 1: H_yx (index 2), outer-dimension shift by -Nx*Ny, Src = SrcHy (25)
+    ref = _listing_update(x0[2][1:], coef[2][1:], coef[14][1:], coef[25][1:],
+                          x0[6], x0[7], (slice(1, None),) + inner[1:],
+                          (slice(0, -1),) + inner[1:])
+    assert np.array_equal(x1[2][1:], ref)
+    # Listing 2: H_zx (index 4), middle-dimension shift by -Nx, no Src
+    ref = _listing_update(x0[4][:, 1:], coef[4][:, 1:], coef[16][:, 1:], None,
+                          x0[6], x0[7], (slice(None), slice(0, -1)),
+                          (slice(None), slice(1, None)))
+    assert np.array_equal(x1[4][:, 1:], ref)
+    # E_xy (index 6): opposite (+1) outer shift, reads the new H_y = H_yx + H_yz
+    ref = _listing_update(x0[6][:-1], coef[6][:-1], coef[18][:-1], coef[26][:-1],
+                          x1[2], x1[3], (slice(1, None),), (slice(0, -1),))
+    assert np.array_equal(x1[6][:-1], ref)
+    # E_xz (index 7): +1 middle shift of H_z, curl sign +1 -> D = G(p) - G(p+e)
+    ref = _listing_update(x0[7][:, :-1], coef[7][:, :-1], coef[19][:, :-1], None,
+                          x1[4], x1[5], (slice(None), slice(0, -1)),
+                          (slice(None), slice(1, None)))
+    assert np.array_equal(x1[7][:, :-1], ref)
+
+
+def test_flop_counts_match_paper(oracle_lib):
+    """Sec. III-A: 22 flops for a Listing-1 update, 20 for Listing 2, 248 per
+    lattice-site update (4 with a source array, 8 without)."""
+    f1, f2 = oracle.flops_per_update(True), oracle.flops_per_update(False)
+    assert (f1, f2) == (22, 20)
+    assert 4 * f1 + 8 * f2 == 248
+
+
+# --------------------------------------------------------------------------
+# Structural invariants
+# --------------------------------------------------------------------------
+def test_linearity_in_source(oracle_lib):
+    """Each iterate from x0 = 0 is linear in the sources (every step is affine
+    in them and x0 = 0)."""
+    pb1 = inputs.random_problem(6, 5, 10, seed=21)
+    pb2 = inputs.random_problem(6, 5, 10, seed=22)
+    a, b = 0.7 - 0.3j, -1.1 + 0.4j
+    mix = {k: a * pb1.sources[k] + b * pb2.sources[k] for k in pb1.sources}
+    c1 = _coef(pb1)
+    c2 = oracle.coeffs(pb1.eps, pb1.sig_e, pb1.sig_h, pb2.sources, pb1.omega, pb1.tau)
+    c3 = oracle.coeffs(pb1.eps, pb1.sig_e, pb1.sig_h, mix, pb1.omega, pb1.tau)
+    x1, x2, x3 = (oracle.zero_fields(pb1.shape) for _ in range(3))
+    for step in (1, 1, 1, 7, 15):
+        oracle.iterate(c1, x1, step)
+        oracle.iterate(c2, x2, step)
+        oracle.iterate(c3, x3, step)
+        assert _rel(x3, a * x1 + b * x2) < 1e-13
+
+
+def test_zero_source_stays_zero(oracle_lib):
+    pb = inputs.solar_cell(8, 8, 20, seed=3, npml=4)
+    pb.sources = {}
+    coef = _coef(pb)
+    assert not np.any(coef[24:])
+    x = oracle.iterate(coef, oracle.zero_fields(pb.shape), 40)
+    assert not np.any(x)
+
+
+def test_flat_stack_xy_invariance(oracle_lib):
+    """Flat layers + uniform x-polarised source: every column is identical,
+    only E_xy and H_yx are non-zero, the other 10 split arrays stay exactly 0,
+    and a 2 x 2 grid gives bit-identical columns (1D reduction)."""
+    pb = inputs.solar_cell(6, 5, 24, seed=5, npml=4, flat=True)
+    coef = _coef(pb)
+    x = oracle.iterate(coef, oracle.zero_fields(pb.shape), 60)
+    for q in range(12):
+        if q in (2, 6):
+            assert np.any(x[q])
+        else:
+            assert not np.any(x[q]), q
+    col = x[:, :, :1, :1]
+    assert np.array_equal(x, np.broadcast_to(col, x.shape))
+    small = inputs.solar_cell(2, 2, 24, seed=5, npml=4, flat=True)
+    assert np.array_equal(small.eps[:, 0, 0], pb.eps[:, 0, 0])
+    xs = oracle.iterate(_coef(small), oracle.zero_fields(small.shape), 60)
+    assert np.array_equal(xs[:, :, :1, :1], col)
+
+
+def test_mirror_symmetry_xy(oracle_lib):
+    """Swapping x <-> y in the geometry and the source polarisation maps
+    E_x <-> E_y, E_z -> E_z (polar) and H_x <-> -H_y, H_z -> -H_z (axial)."""
+    pb = inputs.solar_cell(8, 8, 20, seed=9, npml=4, texture_amp=2)
+    g = inputs.rng(99)
+    pb.eps = pb.eps + 0.3 * g.random(pb.eps.shape)  # break every residual symmetry
+    sx = pb.sources["Ex"] * (1 + 0.2 * g.standard_normal(pb.shape))
+    pb.sources = {"Ex": sx}
+    sw = lambda a: np.ascontiguousarray(np.swapaxes(a, -1, -2))  # noqa: E731
+    pbm = inputs.Problem(eps=sw(pb.eps), sig_e=pb.sig_e, sig_h=pb.sig_h,
+                         sources={"Ey": sw(sx)}, omega=pb.omega, tau=pb.tau)
+    n = 30
+    x = oracle.iterate(_coef(pb), oracle.zero_fields(pb.shape), n)
+    xm = oracle.iterate(_coef(pbm), oracle.zero_fields(pb.shape), n)
+    # index map and sign: mirrored component q' = perm[q], value sign[q] * sw(x[q])
+    perm = {0: 2, 1: 3, 2: 0, 3: 1, 4: 5, 5: 4, 6: 8, 7: 9, 8: 6, 9: 7, 10: 11, 11: 10}
+    scale = np.linalg.norm(x)
+    for q in range(12):
+        s = -1.0 if q < 6 else 1.0
+        assert np.linalg.norm(xm[perm[q]] - s * sw(x[q])) <= 1e-13 * scale, q
+
+
+# --------------------------------------------------------------------------
+# Coefficients: closed forms for sigma = 0
+# --------------------------------------------------------------------------
+def test_coefficients_lossless_closed_form(oracle_lib):
+    nz, ny, nx = 6, 3, 4
+    w, tau, h = 0.37, 0.45, 1.0
+    eps = np.full((nz, ny, nx), 2.5 + 0j)
+    eps[2] = -3.0 + 0j  # back iteration plane, Eq. (5)
+    S = np.ones((nz, ny, nx), dtype=complex)
+    coef = oracle.coeffs(eps, np.zeros(nz), np.zeros(nz),
+                         {"Hx": S, "Hy": S, "Ex": S, "Ey": S}, w, tau, h)
+    e1, e2 = np.exp(-1j * w * tau), np.exp(-1j * w * tau / 2)
+    fwd = np.ones(nz, bool)
+    fwd[2] = False
+    for q in range(6):
+        assert np.allclose(coef[q], e1, rtol=0, atol=1e-15)
+        assert np.allclose(coef[12 + q], tau / h * e2, rtol=0, atol=1e-15)
+    for q in range(6, 12):
+        assert np.allclose(coef[q][fwd], e1, rtol=0, atol=1e-15)
+        assert np.allclose(coef[12 + q][fwd], tau / (2.5 * h) * e2, rtol=0, atol=1e-15)
+        assert np.allclose(coef[q][~fwd], np.conj(e1), rtol=0, atol=1e-15)
+        assert np.allclose(coef[12 + q][~fwd], tau / (3.0 * h) * np.conj(e2), rtol=0, atol=1e-15)
+    assert np.allclose(coef[24], tau * e2, atol=1e-15)      # tau S / e^{iwt/2}
+    assert np.allclose(coef[26][fwd], tau * e1, atol=1e-15)  # tau e^{-iwt} S
+    assert np.allclose(coef[26][~fwd], -tau, atol=1e-15)     # -tau S (Eq. 5)
+
+
+def test_pml_and_loss_damp(oracle_lib):
+    """With sigma > 0 every t has modulus < 1 (passive update)."""
+    pb = inputs.solar_cell(4, 4, 20, seed=2, npml=5, loss_range=(0.1, 0.5))
+    coef = _coef(pb)
+    pml = np.r_[0:5, 15:20]
+    for q in (0, 2):  # H z-difference parts damped inside the PML
+        assert np.all(np.abs(coef[q][pml]) < 1 - 1e-6)
+    for q in range(6, 12):  # E damped by the material loss everywhere
+        assert np.all(np.abs(coef[q]) < 1)
+    assert np.all(np.abs(coef[:12]) <= 1 + 1e-15)
