@@ -1,0 +1,151 @@
+/*
+ * thiim.h -- C-ABI of the MI355X (gfx950) THIIM library.
+ *
+ * The library iterates the Time Harmonic Inverse Iteration Method (THIIM) of
+ * Malas et al., "Optimization of an electromagnetics code with multicore
+ * wavefront diamond blocking and multi-dimensional intra-tile
+ * parallelization" (arXiv:1510.05218): the leapfrog update of Sec. I-A,
+ * Eq. (3)/(4) (Eq. (5) for cells with negative permittivity) on a Yee grid,
+ * with the six field components split into twelve parts as in Eq. (6)/(7)
+ * (Berenger PML), in double-complex arithmetic.  Per cell it keeps the 40
+ * double-complex arrays counted in Sec. III (12 split fields, 28 coefficient
+ * arrays).
+ *
+ * Conventions (all calls):
+ *   - Grid arrays are [nz][ny][nx] (x fastest) of interleaved complex128
+ *     (re, im), the layout of Listings 1 and 2.  N = nx*ny*nz.
+ *   - Units: eps0 = mu0 = c0 = 1, mu_r = 1, grid step h.
+ *   - Split components, in the order used by every field buffer:
+ *       0 H_xy  1 H_xz  2 H_yx  3 H_yz  4 H_zx  5 H_zy
+ *       6 E_xy  7 E_xz  8 E_yx  9 E_yz 10 E_zx 11 E_zy
+ *     (F_ab = part of field component F_a driven by the other field's
+ *     component b, the naming of Listings 1 and 2.)
+ *   - Coefficient arrays, in the order used by thiim_get_coeffs:
+ *       t_q = q, c_q = 12 + q (q = 0..11), Src of H_xy, H_yx, E_xy, E_yx
+ *       = 24..27 (Sec. III: 4*3 + 8*2 = 28 arrays).
+ *   - Boundaries: ghost values beyond the z walls are zero (homogeneous
+ *     Dirichlet, Sec. II-B); x and y are periodic (Sec. I-A, production
+ *     setting) or Dirichlet.
+ *   - Ownership: the caller allocates every buffer (the workspace included);
+ *     the library never allocates device memory.  A context borrows its
+ *     workspace and must be destroyed before the workspace is freed.  Inputs
+ *     are read during thiim_create only.
+ *   - Errors: every int-returning call returns THIIM_OK (0) or a negative
+ *     status; nothing aborts or throws across the ABI.  thiim_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - Streams: work is enqueued on grid.stream (a hipStream_t; NULL = the
+ *     null stream).  thiim_iterate only enqueues; calls documented as
+ *     "synchronising" wait for the stream and report device faults.
+ */
+#ifndef THIIM_H
+#define THIIM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define THIIM_OK 0
+#define THIIM_EINVAL (-1)    /* invalid argument */
+#define THIIM_ENOMEM (-2)    /* workspace too small */
+#define THIIM_EDEVICE (-3)   /* HIP runtime or device error */
+#define THIIM_EDIVERGED (-4) /* non-finite or growing residual */
+#define THIIM_ENOTCONV (-5)  /* iteration limit reached before tolerance */
+
+#define THIIM_PERIODIC 0
+#define THIIM_DIRICHLET 1
+
+/* Sweep implementations of one THIIM iteration (all give the same result;
+ * the fused and blocked forms are bit-identical to the naive one). */
+#define THIIM_KERNEL_AUTO 0    /* library's choice */
+#define THIIM_KERNEL_NAIVE 1   /* one in-place sweep per half-step */
+#define THIIM_KERNEL_FUSED 2   /* H and E half-steps in one HBM pass */
+#define THIIM_KERNEL_BLOCKED 3 /* t_block iterations per HBM pass */
+
+typedef struct thiim_ctx thiim_ctx;
+
+typedef struct {
+    int nx, ny, nz;   /* cells, PML planes included; each >= 2 */
+    int bc_x, bc_y;   /* THIIM_PERIODIC or THIIM_DIRICHLET */
+    double h;         /* grid step (> 0) */
+    double tau;       /* pseudo-time step, 0 < tau <= h / sqrt(3) */
+    int kernel;       /* THIIM_KERNEL_* */
+    int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED (0 = auto) */
+    int tile_x, tile_y; /* x-y tile of the fused / blocked sweeps (0 = auto):
+                         * 64x8, 32x8, 64x4 or 16x16 */
+    int z_chunk;      /* z planes per workgroup stream (0 = auto) */
+    void *stream;     /* hipStream_t */
+} thiim_grid;
+
+typedef struct {
+    /* Device pointer, 2*N doubles: (eps', eps'') per cell.  The relative
+     * permittivity is eps' - i eps'' in the paper's exp(+i w t) convention
+     * (eps'' >= 0 absorbs); eps' > 0 uses the forward update Eq. (3),
+     * eps' < 0 the back iteration Eq. (5); eps' == 0 is rejected. */
+    const double *eps;
+    /* Host pointers, nz doubles each: PML conductivities.  sigma_e[k] is
+     * added to the material conductivity (w eps'') of the two E parts with a
+     * z difference (E_xy, E_yx) at plane k; sigma_h[k] is the magnetic
+     * conductivity of H_xy, H_yx at plane k.  Other parts get no PML term. */
+    const double *sigma_e;
+    const double *sigma_h;
+    /* Device pointers, 2*N doubles each, or NULL for zero: the source terms
+     * S_H and S_E of Eq. (3)/(4) for the x and y components, in the order
+     * S_Hx, S_Hy, S_Ex, S_Ey.  Each enters the Src array of the part with a
+     * z difference (H_xy, H_yx, E_xy, E_yx). */
+    const double *src[4];
+} thiim_coeffs;
+
+/* Bytes of device workspace a context on this grid needs (28 coefficient
+ * arrays, two 12-array field buffers, reduction scratch; 256-B aligned). */
+int thiim_workspace_bytes(const thiim_grid *g, size_t *bytes);
+
+/* Validates the inputs, builds the 28 coefficient arrays on the device
+ * (Eq. (3)-(5) solved for the new value), zeroes the fields (x0 = 0) and
+ * records ||P Phi(0)||_2 for thiim_residual (P: sum of each split pair).
+ * omega: angular frequency in units of c0/h.  Synchronising.  On failure
+ * *out is NULL. */
+int thiim_create(const thiim_grid *g, const thiim_coeffs *m, double omega,
+                 void *workspace, size_t workspace_bytes, thiim_ctx **out);
+
+/* Enqueues n >= 0 THIIM iterations x <- Phi(x) (H half-step, Eq. (4), then
+ * E half-step, Eq. (3)/(5)).  Asynchronous. */
+int thiim_iterate(thiim_ctx *ctx, int n);
+
+/* Relative residual of the physical fields of the current state,
+ * ||P (Phi(x) - x)||_2 / ||P Phi(0)||_2, accumulated in FP64 on the device.
+ * Does not advance x.  Synchronising; THIIM_EDIVERGED if not finite. */
+int thiim_residual(thiim_ctx *ctx, double *rel_res);
+
+/* Iterates until thiim_residual <= tol (checked every check_every
+ * iterations) or max_it iterations.  *iters, *rel_res may be NULL.
+ * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
+int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
+                int *iters, double *rel_res);
+
+/* Device-to-device copies of the 12 split fields, one buffer of 12*2*N
+ * doubles in component order.  get: synchronising. */
+int thiim_get_fields(thiim_ctx *ctx, double *dst);
+int thiim_set_fields(thiim_ctx *ctx, const double *src);
+
+/* Device copy of the 28 coefficient arrays (28*2*N doubles).  Synchronising. */
+int thiim_get_coeffs(thiim_ctx *ctx, double *dst);
+
+/* Iterations done since create / set_fields. */
+int thiim_iterations(const thiim_ctx *ctx, long long *n);
+
+/* Releases the context (not the workspace).  NULL is allowed. */
+void thiim_destroy(thiim_ctx *ctx);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *thiim_last_error(void);
+
+/* Name of a status code. */
+const char *thiim_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THIIM_H */

@@ -1,0 +1,376 @@
+// C-ABI of the THIIM library: context, validation, workspace layout and the
+// dispatch of one iteration to the naive, fused or temporally blocked sweeps.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/thiim.h"
+#include "thiim_kernels.h"
+
+using thiim::Geo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(THIIM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kResidBlocks = 1024;
+constexpr size_t kHeaderBytes = 4096;  // flag, reduction output
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    long long N, S;  // cells, array stride (double2)
+    size_t off_sig;  // 2*nz doubles
+    size_t off_part; // 2*kResidBlocks doubles
+    size_t off_coef, off_a, off_b;
+    size_t total;
+};
+
+Layout layout_of(const thiim_grid* g) {
+    Layout L;
+    L.N = (long long)g->nx * g->ny * g->nz;
+    L.S = (long long)align_up((size_t)L.N, kAlign / 16);
+    size_t off = kHeaderBytes;
+    L.off_sig = off;
+    off = align_up(off + 2 * sizeof(double) * g->nz, kAlign);
+    L.off_part = off;
+    off = align_up(off + 2 * sizeof(double) * kResidBlocks, kAlign);
+    L.off_coef = off;
+    off += (size_t)28 * L.S * 16;
+    L.off_a = off;
+    off += (size_t)12 * L.S * 16;
+    L.off_b = off;
+    off += (size_t)12 * L.S * 16;
+    L.total = off;
+    return L;
+}
+
+int check_grid(const thiim_grid* g) {
+    if (!g) return fail(THIIM_EINVAL, "grid is NULL");
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2)
+        return fail(THIIM_EINVAL, "nx, ny, nz must each be >= 2");
+    if ((long long)g->nx * g->ny * g->nz > (1LL << 40))
+        return fail(THIIM_EINVAL, "grid too large");
+    if ((g->bc_x != THIIM_PERIODIC && g->bc_x != THIIM_DIRICHLET) ||
+        (g->bc_y != THIIM_PERIODIC && g->bc_y != THIIM_DIRICHLET))
+        return fail(THIIM_EINVAL, "bc_x / bc_y must be PERIODIC or DIRICHLET");
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(THIIM_EINVAL, "h must be > 0");
+    if (!(g->tau > 0.0) || !(g->tau <= g->h / std::sqrt(3.0) * (1.0 + 1e-12)))
+        return fail(THIIM_EINVAL, "tau must satisfy 0 < tau <= h/sqrt(3) (CFL)");
+    if (g->kernel < THIIM_KERNEL_AUTO || g->kernel > THIIM_KERNEL_BLOCKED)
+        return fail(THIIM_EINVAL, "unknown kernel");
+    if (g->t_block < 0 || g->t_block > 8) return fail(THIIM_EINVAL, "t_block must be in [0, 8]");
+    if (g->z_chunk < 0) return fail(THIIM_EINVAL, "z_chunk must be >= 0");
+    const bool tile_auto = g->tile_x == 0 && g->tile_y == 0;
+    const bool tile_ok = (g->tile_x == 64 && g->tile_y == 8) || (g->tile_x == 32 && g->tile_y == 8) ||
+                         (g->tile_x == 64 && g->tile_y == 4) || (g->tile_x == 16 && g->tile_y == 16);
+    if (!tile_auto && !tile_ok)
+        return fail(THIIM_EINVAL, "tile must be 0x0 (auto), 64x8, 32x8, 64x4 or 16x16");
+    return THIIM_OK;
+}
+
+}  // namespace
+
+struct thiim_ctx {
+    thiim_grid g;
+    Geo geo;
+    Layout L;
+    double omega;
+    hipStream_t stream;
+    int device;
+    char* ws;
+    double2* coef;
+    double2* F[2];
+    int cur;  // index of the buffer holding the current state
+    double* sig_dev;
+    double* part;
+    double* out;  // [2] reduction output
+    int* flag;
+    double phi0_norm;
+    long long iters;
+    int kernel;  // resolved THIIM_KERNEL_*
+    int tile_x, tile_y, z_chunk;
+};
+
+namespace {
+
+int resolve_tiles(thiim_ctx* c) {
+    const thiim_grid& g = c->g;
+    if (g.tile_x == 0) {
+        if (g.nx >= 48) { c->tile_x = 64; c->tile_y = 8; }
+        else if (g.nx >= 24) { c->tile_x = 32; c->tile_y = 8; }
+        else { c->tile_x = 16; c->tile_y = 16; }
+    } else {
+        c->tile_x = g.tile_x;
+        c->tile_y = g.tile_y;
+    }
+    if (g.z_chunk > 0) {
+        c->z_chunk = g.z_chunk;
+    } else {
+        // enough workgroups to cover the 256 CUs several times over
+        const long long tiles = (long long)((g.nx + c->tile_x - 1) / c->tile_x) *
+                                ((g.ny + c->tile_y - 1) / c->tile_y);
+        int nch = (int)((2048 + tiles - 1) / tiles);
+        if (nch < 1) nch = 1;
+        int zc = (g.nz + nch - 1) / nch;
+        if (zc < 32) zc = 32;
+        c->z_chunk = zc;
+    }
+    c->kernel = g.kernel == THIIM_KERNEL_AUTO ? THIIM_KERNEL_FUSED : g.kernel;
+    if (c->kernel == THIIM_KERNEL_BLOCKED) c->kernel = THIIM_KERNEL_FUSED;
+    return THIIM_OK;
+}
+
+// One THIIM iteration from buffer `src` into buffer `dst` (src != dst).
+hipError_t one_pass(thiim_ctx* c, int src, int dst) {
+    return thiim::launch_fused(c->coef, c->F[src], c->F[dst], c->geo, c->tile_x, c->tile_y,
+                               c->z_chunk, c->stream);
+}
+
+// r2 = ||P(F[b] - F[a])||^2, b2 = ||P F[b]||^2 (synchronising)
+int reduce(thiim_ctx* c, int a, int b, double* r2, double* b2) {
+    hipError_t e = thiim::launch_resid(c->F[a], c->F[b], c->L.S, c->L.N, c->part,
+                                       kResidBlocks, c->out, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual launch");
+    double host[2];
+    e = hipMemcpyAsync(host, c->out, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual copy");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual sync");
+    *r2 = host[0];
+    *b2 = host[1];
+    return THIIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int thiim_workspace_bytes(const thiim_grid* g, size_t* bytes) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!bytes) return fail(THIIM_EINVAL, "bytes is NULL");
+    *bytes = layout_of(g).total;
+    return THIIM_OK;
+}
+
+int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void* workspace,
+                 size_t workspace_bytes, thiim_ctx** out) {
+    if (!out) return fail(THIIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!m || !m->eps || !m->sigma_e || !m->sigma_h)
+        return fail(THIIM_EINVAL, "coeffs, eps, sigma_e and sigma_h are required");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(THIIM_EINVAL, "omega must be > 0");
+    for (int k = 0; k < g->nz; ++k) {
+        if (!std::isfinite(m->sigma_e[k]) || !std::isfinite(m->sigma_h[k]) ||
+            m->sigma_e[k] < 0.0 || m->sigma_h[k] < 0.0)
+            return fail(THIIM_EINVAL, "PML conductivities must be finite and >= 0");
+    }
+    const Layout L = layout_of(g);
+    if (!workspace) return fail(THIIM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % kAlign) return fail(THIIM_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(THIIM_ENOMEM, "workspace smaller than thiim_workspace_bytes()");
+    if (((uintptr_t)m->eps) % 16) return fail(THIIM_EINVAL, "eps must be 16-byte aligned");
+    for (int s = 0; s < 4; ++s)
+        if (m->src[s] && ((uintptr_t)m->src[s]) % 16)
+            return fail(THIIM_EINVAL, "source arrays must be 16-byte aligned");
+
+    thiim_ctx* c = new (std::nothrow) thiim_ctx();
+    if (!c) return fail(THIIM_EINVAL, "out of host memory");
+    c->g = *g;
+    c->L = L;
+    c->omega = omega;
+    c->stream = (hipStream_t)g->stream;
+    hipGetDevice(&c->device);
+    c->ws = (char*)workspace;
+    c->flag = (int*)c->ws;
+    c->out = (double*)(c->ws + 256);
+    c->sig_dev = (double*)(c->ws + L.off_sig);
+    c->part = (double*)(c->ws + L.off_part);
+    c->coef = (double2*)(c->ws + L.off_coef);
+    c->F[0] = (double2*)(c->ws + L.off_a);
+    c->F[1] = (double2*)(c->ws + L.off_b);
+    c->cur = 0;
+    c->iters = 0;
+    c->geo = Geo{g->nx, g->ny, g->nz, g->bc_x, g->bc_y, L.S};
+    resolve_tiles(c);
+
+    auto bail = [&](int status) {
+        delete c;
+        return status;
+    };
+    hipError_t e;
+    e = hipMemsetAsync(c->ws, 0, kHeaderBytes, c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "memset"));
+    e = hipMemcpyAsync(c->sig_dev, m->sigma_e, sizeof(double) * g->nz, hipMemcpyHostToDevice,
+                       c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->sig_dev + g->nz, m->sigma_h, sizeof(double) * g->nz,
+                           hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "profile copy"));
+
+    thiim::CoefArgs a;
+    a.eps = (const double2*)m->eps;
+    a.sig_e = c->sig_dev;
+    a.sig_h = c->sig_dev + g->nz;
+    for (int s = 0; s < 4; ++s) a.src[s] = (const double2*)m->src[s];
+    a.coef = c->coef;
+    a.S = L.S;
+    a.N = L.N;
+    a.nxy = (long long)g->nx * g->ny;
+    a.tau = g->tau;
+    a.h = g->h;
+    a.omega = omega;
+    const double wt = omega * g->tau;
+    a.ph = make_double2(std::cos(wt), std::sin(wt));
+    a.phc = make_double2(std::cos(wt), -std::sin(wt));
+    a.ph2 = make_double2(std::cos(wt / 2), std::sin(wt / 2));
+    a.ph2c = make_double2(std::cos(wt / 2), -std::sin(wt / 2));
+    a.flag = c->flag;
+    e = thiim::launch_coeffs(a, c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "coefficient launch"));
+    e = thiim::launch_fill_zero(c->F[0], 24 * L.S, c->stream);  // both buffers
+    if (e != hipSuccess) return bail(hip_fail(e, "zero fields"));
+    int flag = 0;
+    e = hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "create sync"));
+    if (flag) return bail(fail(THIIM_EINVAL, "eps has a non-finite value or eps' == 0"));
+
+    // ||P Phi(0)||: one iteration from the zero state
+    e = one_pass(c, 0, 1);
+    if (e != hipSuccess) return bail(hip_fail(e, "phi(0) launch"));
+    double r2 = 0, b2 = 0;
+    rc = reduce(c, 0, 1, &r2, &b2);
+    if (rc) return bail(rc);
+    c->phi0_norm = std::sqrt(b2);
+    if (!std::isfinite(c->phi0_norm)) return bail(fail(THIIM_EINVAL, "non-finite source response"));
+    *out = c;
+    return THIIM_OK;
+}
+
+int thiim_iterate(thiim_ctx* c, int n) {
+    if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(THIIM_EINVAL, "n must be >= 0");
+    for (int it = 0; it < n; ++it) {
+        hipError_t e;
+        if (c->kernel == THIIM_KERNEL_NAIVE) {
+            e = thiim::launch_naive(c->coef, c->F[c->cur], c->geo, c->z_chunk, c->stream);
+        } else {
+            e = one_pass(c, c->cur, 1 - c->cur);
+            c->cur = 1 - c->cur;
+        }
+        if (e != hipSuccess) return hip_fail(e, "iterate launch");
+        c->iters++;
+    }
+    return THIIM_OK;
+}
+
+int thiim_residual(thiim_ctx* c, double* rel_res) {
+    if (!c || !rel_res) return fail(THIIM_EINVAL, "ctx / rel_res is NULL");
+    const int other = 1 - c->cur;
+    hipError_t e = one_pass(c, c->cur, other);
+    if (e != hipSuccess) return hip_fail(e, "residual pass");
+    double r2 = 0, b2 = 0;
+    int rc = reduce(c, c->cur, other, &r2, &b2);
+    if (rc) return rc;
+    const double r = std::sqrt(r2) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
+    *rel_res = r;
+    if (!std::isfinite(r)) return fail(THIIM_EDIVERGED, "residual is not finite");
+    return THIIM_OK;
+}
+
+int thiim_solve(thiim_ctx* c, double tol, int max_it, int check_every, int* iters,
+                double* rel_res) {
+    if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
+    if (!(tol > 0.0) || max_it < 0 || check_every < 1)
+        return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1");
+    int done = 0;
+    double r = INFINITY;
+    int rc = thiim_residual(c, &r);
+    while (rc == THIIM_OK && r > tol && done < max_it) {
+        const int step = check_every < max_it - done ? check_every : max_it - done;
+        rc = thiim_iterate(c, step);
+        if (rc) break;
+        done += step;
+        rc = thiim_residual(c, &r);
+    }
+    if (iters) *iters = done;
+    if (rel_res) *rel_res = r;
+    if (rc) return rc;
+    if (r > tol) return fail(THIIM_ENOTCONV, "iteration limit reached before tolerance");
+    return THIIM_OK;
+}
+
+int thiim_get_fields(thiim_ctx* c, double* dst) {
+    if (!c || !dst) return fail(THIIM_EINVAL, "ctx / dst is NULL");
+    for (int q = 0; q < 12; ++q) {
+        hipError_t e = hipMemcpyAsync(dst + 2 * q * c->L.N, c->F[c->cur] + q * c->L.S,
+                                      16 * c->L.N, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "get_fields");
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? THIIM_OK : hip_fail(e, "get_fields sync");
+}
+
+int thiim_set_fields(thiim_ctx* c, const double* src) {
+    if (!c || !src) return fail(THIIM_EINVAL, "ctx / src is NULL");
+    for (int q = 0; q < 12; ++q) {
+        hipError_t e = hipMemcpyAsync(c->F[c->cur] + q * c->L.S, src + 2 * q * c->L.N,
+                                      16 * c->L.N, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "set_fields");
+    }
+    c->iters = 0;
+    return THIIM_OK;
+}
+
+int thiim_get_coeffs(thiim_ctx* c, double* dst) {
+    if (!c || !dst) return fail(THIIM_EINVAL, "ctx / dst is NULL");
+    for (int q = 0; q < 28; ++q) {
+        hipError_t e = hipMemcpyAsync(dst + 2 * q * c->L.N, c->coef + q * c->L.S, 16 * c->L.N,
+                                      hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "get_coeffs");
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? THIIM_OK : hip_fail(e, "get_coeffs sync");
+}
+
+int thiim_iterations(const thiim_ctx* c, long long* n) {
+    if (!c || !n) return fail(THIIM_EINVAL, "ctx / n is NULL");
+    *n = c->iters;
+    return THIIM_OK;
+}
+
+void thiim_destroy(thiim_ctx* c) { delete c; }
+
+const char* thiim_last_error(void) { return g_last_error.c_str(); }
+
+const char* thiim_status_str(int s) {
+    switch (s) {
+        case THIIM_OK: return "THIIM_OK";
+        case THIIM_EINVAL: return "THIIM_EINVAL";
+        case THIIM_ENOMEM: return "THIIM_ENOMEM";
+        case THIIM_EDEVICE: return "THIIM_EDEVICE";
+        case THIIM_EDIVERGED: return "THIIM_EDIVERGED";
+        case THIIM_ENOTCONV: return "THIIM_ENOTCONV";
+        default: return "THIIM_UNKNOWN";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+"""Python binding of the THIIM C-ABI (``include/thiim.h``): ctypes argument
+marshalling only.  Every step of the iteration runs in the HIP kernels of
+``libthiim.so``; torch provides device memory and the stream.  There is no
+fallback: without the built library (or without a GPU) the calls raise.
+
+Module-level functions carry the C names (``thiim_create``, ``thiim_iterate``
+...); :class:`Solver` bundles them with the torch-owned buffers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libthiim.so")
+
+THIIM_OK = 0
+THIIM_EINVAL = -1
+THIIM_ENOMEM = -2
+THIIM_EDEVICE = -3
+THIIM_EDIVERGED = -4
+THIIM_ENOTCONV = -5
+PERIODIC, DIRICHLET = 0, 1
+KERNELS = {"auto": 0, "naive": 1, "fused": 2, "blocked": 3}
+
+SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
+           "thiim_residual", "thiim_solve", "thiim_get_fields",
+           "thiim_set_fields", "thiim_get_coeffs", "thiim_iterations",
+           "thiim_destroy", "thiim_last_error", "thiim_status_str")
+
+
+class ThiimError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("h", ctypes.c_double), ("tau", ctypes.c_double),
+                ("kernel", ctypes.c_int), ("t_block", ctypes.c_int),
+                ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+                ("z_chunk", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class Coeffs(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_void_p),
+                ("sigma_e", ctypes.POINTER(ctypes.c_double)),
+                ("sigma_h", ctypes.POINTER(ctypes.c_double)),
+                ("src", ctypes.c_void_p * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libthiim.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1510_05218_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.thiim_workspace_bytes.argtypes = [P(Grid), P(ctypes.c_size_t)]
+        L.thiim_create.argtypes = [P(Grid), P(Coeffs), d, vp, ctypes.c_size_t, P(vp)]
+        L.thiim_iterate.argtypes = [vp, i]
+        L.thiim_residual.argtypes = [vp, P(d)]
+        L.thiim_solve.argtypes = [vp, d, i, i, P(i), P(d)]
+        L.thiim_get_fields.argtypes = [vp, vp]
+        L.thiim_set_fields.argtypes = [vp, vp]
+        L.thiim_get_coeffs.argtypes = [vp, vp]
+        L.thiim_iterations.argtypes = [vp, P(ctypes.c_longlong)]
+        L.thiim_destroy.argtypes = [vp]
+        L.thiim_destroy.restype = None
+        L.thiim_last_error.restype = ctypes.c_char_p
+        L.thiim_status_str.argtypes = [i]
+        L.thiim_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().thiim_status_str(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().thiim_last_error().decode()
+
+
+def _check(rc):
+    if rc != THIIM_OK:
+        raise ThiimError(rc, last_error())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# the C calls, one wrapper each
+# ---------------------------------------------------------------------------
+def thiim_workspace_bytes(grid: Grid) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().thiim_workspace_bytes(ctypes.byref(grid), ctypes.byref(n)))
+    return n.value
+
+
+def thiim_create(grid: Grid, coeffs: Coeffs, omega: float, workspace_ptr: int,
+                 workspace_bytes: int):
+    ctx = ctypes.c_void_p()
+    _check(lib().thiim_create(ctypes.byref(grid), ctypes.byref(coeffs), float(omega),
+                              ctypes.c_void_p(workspace_ptr), workspace_bytes,
+                              ctypes.byref(ctx)))
+    return ctx
+
+
+def thiim_iterate(ctx, n: int):
+    _check(lib().thiim_iterate(ctx, int(n)))
+
+
+def thiim_residual(ctx) -> float:
+    r = ctypes.c_double()
+    _check(lib().thiim_residual(ctx, ctypes.byref(r)))
+    return r.value
+
+
+def thiim_solve(ctx, tol: float, max_it: int, check_every: int = 50):
+    """Returns (status, iterations, rel_res); ENOTCONV is returned, not raised."""
+    it, r = ctypes.c_int(), ctypes.c_double()
+    rc = lib().thiim_solve(ctx, float(tol), int(max_it), int(check_every),
+                           ctypes.byref(it), ctypes.byref(r))
+    if rc not in (THIIM_OK, THIIM_ENOTCONV):
+        _check(rc)
+    return rc, it.value, r.value
+
+
+def thiim_get_fields(ctx, dst_ptr: int):
+    _check(lib().thiim_get_fields(ctx, ctypes.c_void_p(dst_ptr)))
+
+
+def thiim_set_fields(ctx, src_ptr: int):
+    _check(lib().thiim_set_fields(ctx, ctypes.c_void_p(src_ptr)))
+
+
+def thiim_get_coeffs(ctx, dst_ptr: int):
+    _check(lib().thiim_get_coeffs(ctx, ctypes.c_void_p(dst_ptr)))
+
+
+def thiim_iterations(ctx) -> int:
+    n = ctypes.c_longlong()
+    _check(lib().thiim_iterations(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def thiim_destroy(ctx):
+    lib().thiim_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper owning the torch buffers
+# ---------------------------------------------------------------------------
+def make_grid(shape, tau=0.5, h=1.0, bcx=PERIODIC, bcy=PERIODIC, kernel="auto",
+              t_block=0, tile=(0, 0), z_chunk=0, stream=None) -> Grid:
+    nz, ny, nx = shape
+    return Grid(nx, ny, nz, bcx, bcy, h, tau, KERNELS[kernel], t_block,
+                tile[0], tile[1], z_chunk, stream)
+
+
+class Solver:
+    """One THIIM problem resident on the GPU.
+
+    ``problem`` is an :class:`paper_1510_05218_amd.inputs.Problem` (material
+    data, PML profiles, sources, omega, tau).  Its ``eps`` and source arrays
+    may be numpy arrays (copied to the device for ``thiim_create`` and
+    released afterwards) or complex128 device tensors (used in place)."""
+
+    def __init__(self, problem, kernel="auto", t_block=0, tile=(0, 0), z_chunk=0,
+                 device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the THIIM library needs an MI355X GPU (no CPU path)")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.shape = tuple(problem.eps.shape)
+        nz, ny, nx = self.shape
+        self.N = nx * ny * nz
+        self.grid = make_grid(self.shape, problem.tau, problem.h, problem.bcx,
+                              problem.bcy, kernel, t_block, tile, z_chunk,
+                              self.stream.cuda_stream)
+        self.ws_bytes = thiim_workspace_bytes(self.grid)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(self.stream):
+            eps = self._to_dev(problem.eps)
+            srcs = [self._to_dev(problem.sources[k]) if k in problem.sources else None
+                    for k in ("Hx", "Hy", "Ex", "Ey")]
+        self._sig_e = np.ascontiguousarray(problem.sig_e, dtype=np.float64)
+        self._sig_h = np.ascontiguousarray(problem.sig_h, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        co = Coeffs(eps.data_ptr(), self._sig_e.ctypes.data_as(dp),
+                    self._sig_h.ctypes.data_as(dp),
+                    (ctypes.c_void_p * 4)(*[s.data_ptr() if s is not None else None
+                                            for s in srcs]))
+        self.omega = float(problem.omega)
+        self.ctx = thiim_create(self.grid, co, self.omega, self.workspace.data_ptr(),
+                                self.ws_bytes)
+        del eps, srcs
+
+    def _to_dev(self, a):
+        """Device complex128 tensor for an input array (no copy if it is one)."""
+        if isinstance(a, self.torch.Tensor):
+            return a.to(self.device, self.torch.complex128).contiguous()
+        t = self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+        return t.to(self.device, non_blocking=False)
+
+    # -- calls
+    def iterate(self, n):
+        thiim_iterate(self.ctx, n)
+
+    def residual(self):
+        return thiim_residual(self.ctx)
+
+    def solve(self, tol, max_it, check_every=50):
+        return thiim_solve(self.ctx, tol, max_it, check_every)
+
+    def fields(self):
+        """The 12 split fields, complex128 tensor (12, nz, ny, nx) on the GPU."""
+        out = self.torch.empty((12,) + self.shape, dtype=self.torch.complex128,
+                               device=self.device)
+        thiim_get_fields(self.ctx, out.data_ptr())
+        return out
+
+    def set_fields(self, x):
+        x = x.to(self.device, self.torch.complex128).contiguous()
+        assert tuple(x.shape) == (12,) + self.shape
+        thiim_set_fields(self.ctx, x.data_ptr())
+        self.stream.synchronize()
+
+    def coeffs(self):
+        out = self.torch.empty((28,) + self.shape, dtype=self.torch.complex128,
+                               device=self.device)
+        thiim_get_coeffs(self.ctx, out.data_ptr())
+        return out
+
+    @property
+    def iterations(self):
+        return thiim_iterations(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            thiim_destroy(self.ctx)
+            self.ctx = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,69 @@
+"""Host-side checks of the C-ABI library (no GPU, no compute calls): it loads,
+exports every symbol the header declares, sizes workspaces and rejects bad
+arguments before touching the device."""
+import os
+import re
+
+import pytest
+
+from paper_1510_05218_amd import thiim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "thiim.h")).read()
+    return sorted(set(re.findall(r"\b(thiim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = thiim.lib()
+    declared = _declared_symbols()
+    assert set(declared) == set(thiim.SYMBOLS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_layout():
+    g = thiim.make_grid((36, 24, 24))
+    n = 24 * 24 * 36
+    b = thiim.thiim_workspace_bytes(g)
+    assert b >= 52 * 16 * n          # 28 coefficient + 2 x 12 field arrays
+    assert b < 52 * 16 * n + 2 ** 20
+    g512 = thiim.make_grid((512, 512, 512))
+    b512 = thiim.thiim_workspace_bytes(g512)
+    assert abs(b512 - 52 * 16 * 512 ** 3) < 2 ** 20  # 111.7 GB
+
+
+@pytest.mark.parametrize("field,value", [("nx", 1), ("nz", 0), ("tau", 0.6), ("tau", 0.0),
+                                         ("h", -1.0), ("bc_x", 2), ("kernel", 9),
+                                         ("tile_x", 48), ("z_chunk", -1), ("t_block", 99)])
+def test_invalid_grid_rejected(field, value):
+    g = thiim.make_grid((10, 10, 10))
+    setattr(g, field, value)
+    with pytest.raises(thiim.ThiimError) as e:
+        thiim.thiim_workspace_bytes(g)
+    assert e.value.status == thiim.THIIM_EINVAL
+    assert thiim.last_error()
+
+
+def test_create_rejects_missing_inputs_without_device():
+    g = thiim.make_grid((8, 8, 8))
+    with pytest.raises(thiim.ThiimError) as e:
+        thiim.thiim_create(g, thiim.Coeffs(), 0.3, 0, 0)
+    assert e.value.status == thiim.THIIM_EINVAL
+
+
+def test_status_strings():
+    for code, name in [(0, "THIIM_OK"), (-1, "THIIM_EINVAL"), (-2, "THIIM_ENOMEM"),
+                       (-3, "THIIM_EDEVICE"), (-4, "THIIM_EDIVERGED"),
+                       (-5, "THIIM_ENOTCONV")]:
+        assert thiim.status_str(code) == name
+
+
+def test_solver_refuses_cpu():
+    from paper_1510_05218_amd import inputs
+
+    pb = inputs.solar_cell(8, 8, 16, seed=1, npml=3)
+    with pytest.raises(RuntimeError):
+        thiim.Solver(pb, device="cpu")
