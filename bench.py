@@ -32,7 +32,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_LUP = {
     "naive": 1024,   # two sweeps: (26 reads + 6 writes) x 16 B each
     "fused": 832,    # one pass: 40 reads + 12 writes, x 16 B
+    "blocked": 416,  # one pass per two iterations: 40 reads + 12 writes, x 16 B
 }
+ITERS_PER_LAUNCH = {"naive": 0.5, "fused": 1, "blocked": 2}
 
 
 def log(*a):
@@ -106,12 +108,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--kernel", default="fused", choices=["naive", "fused"])
+    ap.add_argument("--kernel", default="blocked", choices=["naive", "fused", "blocked"])
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--iters", type=int, default=100)
-    ap.add_argument("--compare", default="naive",
+    ap.add_argument("--compare", default="fused,naive",
                     help="comma list of extra kernels timed for context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 4 GiB device copy first (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -135,6 +139,16 @@ def main():
     dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
     torch.cuda.synchronize()
 
+    if args.calib_copy:
+        a = torch.empty(2 ** 32, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 4 GiB read + 4 GiB written")
+        del a, b
+        torch.cuda.empty_cache()
+
     results = {}
     for kernel in [args.kernel] + [k for k in args.compare.split(",") if k and k != args.kernel]:
         step_ms, iter_ms, res = time_kernel_run(torch, thiim, dev, kernel, args.iters,
@@ -147,10 +161,11 @@ def main():
     ms_per_step = sum(step_ms) / len(step_ms)
     it_ms = sum(iter_ms) / len(iter_ms)
     glups = N * args.iters / (ms_per_step * 1e-3) / 1e9
-    # dominant kernel: the sweep; one launch per iteration (fused) or two (naive)
-    launches = 1 if args.kernel == "fused" else 2
-    bytes_per_launch = BYTES_PER_LUP[args.kernel] * N / launches
-    achieved = bytes_per_launch / (it_ms / launches * 1e-3) / 1e9
+    # dominant kernel: the sweep (two launches per iteration for naive, one per
+    # iteration for fused, one per two iterations for blocked)
+    ipl = ITERS_PER_LAUNCH[args.kernel]
+    bytes_per_launch = BYTES_PER_LUP[args.kernel] * N * ipl
+    achieved = bytes_per_launch / (it_ms * ipl * 1e-3) / 1e9
     extra = {}
     for k, (sm, im, r) in results.items():
         extra[k] = {"ms_per_iteration": sum(im) / len(im),

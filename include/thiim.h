@@ -71,9 +71,11 @@ typedef struct {
     double h;         /* grid step (> 0) */
     double tau;       /* pseudo-time step, 0 < tau <= h / sqrt(3) */
     int kernel;       /* THIIM_KERNEL_* */
-    int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED (0 = auto) */
-    int tile_x, tile_y; /* x-y tile of the fused / blocked sweeps (0 = auto):
-                         * 64x8, 32x8, 64x4 or 16x16 */
+    int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED: 0 (auto,
+                       * = 2), 1 or 2; a remainder runs through the fused sweep */
+    int tile_x, tile_y; /* fused sweep: tile 64x8, 32x8, 64x4 or 16x16; blocked
+                         * sweep: region 64x8 or 64x6 (columns x rows) of which
+                         * the centre (64-2T) x (rows-2T) is stored; 0x0 = auto */
     int z_chunk;      /* z planes per workgroup stream (0 = auto) */
     void *stream;     /* hipStream_t */
 } thiim_grid;

@@ -72,13 +72,21 @@ int check_grid(const thiim_grid* g) {
         return fail(THIIM_EINVAL, "tau must satisfy 0 < tau <= h/sqrt(3) (CFL)");
     if (g->kernel < THIIM_KERNEL_AUTO || g->kernel > THIIM_KERNEL_BLOCKED)
         return fail(THIIM_EINVAL, "unknown kernel");
-    if (g->t_block < 0 || g->t_block > 8) return fail(THIIM_EINVAL, "t_block must be in [0, 8]");
+    if (g->t_block < 0 || g->t_block > 2) return fail(THIIM_EINVAL, "t_block must be 0 (auto), 1 or 2");
     if (g->z_chunk < 0) return fail(THIIM_EINVAL, "z_chunk must be >= 0");
     const bool tile_auto = g->tile_x == 0 && g->tile_y == 0;
-    const bool tile_ok = (g->tile_x == 64 && g->tile_y == 8) || (g->tile_x == 32 && g->tile_y == 8) ||
-                         (g->tile_x == 64 && g->tile_y == 4) || (g->tile_x == 16 && g->tile_y == 16);
-    if (!tile_auto && !tile_ok)
-        return fail(THIIM_EINVAL, "tile must be 0x0 (auto), 64x8, 32x8, 64x4 or 16x16");
+    if (g->kernel == THIIM_KERNEL_BLOCKED) {
+        if (!tile_auto && !(g->tile_x == 64 && (g->tile_y == 8 || g->tile_y == 6)))
+            return fail(THIIM_EINVAL, "blocked kernel: tile must be 0x0 (auto), 64x8 or 64x6 "
+                                      "(region columns x rows)");
+    } else {
+        const bool tile_ok = (g->tile_x == 64 && g->tile_y == 8) ||
+                             (g->tile_x == 32 && g->tile_y == 8) ||
+                             (g->tile_x == 64 && g->tile_y == 4) ||
+                             (g->tile_x == 16 && g->tile_y == 16);
+        if (!tile_auto && !tile_ok)
+            return fail(THIIM_EINVAL, "tile must be 0x0 (auto), 64x8, 32x8, 64x4 or 16x16");
+    }
     return THIIM_OK;
 }
 
@@ -102,35 +110,44 @@ struct thiim_ctx {
     double phi0_norm;
     long long iters;
     int kernel;  // resolved THIIM_KERNEL_*
-    int tile_x, tile_y, z_chunk;
+    int tile_x, tile_y, z_chunk;      // fused sweep
+    int t_block, region_y, bz_chunk;  // blocked sweep
 };
 
 namespace {
 
+int auto_chunk(const thiim_grid& g, long long tiles) {
+    // enough workgroups to cover the 256 CUs several times over
+    int nch = (int)((2048 + tiles - 1) / tiles);
+    if (nch < 1) nch = 1;
+    int zc = (g.nz + nch - 1) / nch;
+    return zc < 32 ? 32 : zc;
+}
+
 int resolve_tiles(thiim_ctx* c) {
     const thiim_grid& g = c->g;
-    if (g.tile_x == 0) {
-        if (g.nx >= 48) { c->tile_x = 64; c->tile_y = 8; }
-        else if (g.nx >= 24) { c->tile_x = 32; c->tile_y = 8; }
-        else { c->tile_x = 16; c->tile_y = 16; }
-    } else {
+    c->kernel = g.kernel == THIIM_KERNEL_AUTO ? THIIM_KERNEL_FUSED : g.kernel;
+    if (c->kernel != THIIM_KERNEL_BLOCKED && g.tile_x != 0) {
         c->tile_x = g.tile_x;
         c->tile_y = g.tile_y;
-    }
-    if (g.z_chunk > 0) {
-        c->z_chunk = g.z_chunk;
+    } else if (g.nx >= 48) {
+        c->tile_x = 64;
+        c->tile_y = 8;
+    } else if (g.nx >= 24) {
+        c->tile_x = 32;
+        c->tile_y = 8;
     } else {
-        // enough workgroups to cover the 256 CUs several times over
-        const long long tiles = (long long)((g.nx + c->tile_x - 1) / c->tile_x) *
-                                ((g.ny + c->tile_y - 1) / c->tile_y);
-        int nch = (int)((2048 + tiles - 1) / tiles);
-        if (nch < 1) nch = 1;
-        int zc = (g.nz + nch - 1) / nch;
-        if (zc < 32) zc = 32;
-        c->z_chunk = zc;
+        c->tile_x = 16;
+        c->tile_y = 16;
     }
-    c->kernel = g.kernel == THIIM_KERNEL_AUTO ? THIIM_KERNEL_FUSED : g.kernel;
-    if (c->kernel == THIIM_KERNEL_BLOCKED) c->kernel = THIIM_KERNEL_FUSED;
+    const long long tiles = (long long)((g.nx + c->tile_x - 1) / c->tile_x) *
+                            ((g.ny + c->tile_y - 1) / c->tile_y);
+    c->z_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, tiles);
+    c->t_block = g.t_block > 0 ? g.t_block : 2;
+    c->region_y = (c->kernel == THIIM_KERNEL_BLOCKED && g.tile_y != 0) ? g.tile_y : 8;
+    const int ox = 64 - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
+    const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
+    c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles);
     return THIIM_OK;
 }
 
@@ -197,7 +214,7 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->L = L;
     c->omega = omega;
     c->stream = (hipStream_t)g->stream;
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
     c->ws = (char*)workspace;
     c->flag = (int*)c->ws;
     c->out = (double*)(c->ws + 256);
@@ -272,6 +289,13 @@ int thiim_iterate(thiim_ctx* c, int n) {
         hipError_t e;
         if (c->kernel == THIIM_KERNEL_NAIVE) {
             e = thiim::launch_naive(c->coef, c->F[c->cur], c->geo, c->z_chunk, c->stream);
+        } else if (c->kernel == THIIM_KERNEL_BLOCKED && c->t_block > 1 &&
+                   n - it >= c->t_block) {
+            e = thiim::launch_blocked(c->coef, c->F[c->cur], c->F[1 - c->cur], c->geo,
+                                      c->t_block, c->region_y, c->bz_chunk, c->stream);
+            c->cur = 1 - c->cur;
+            it += c->t_block - 1;
+            c->iters += c->t_block - 1;
         } else {
             e = one_pass(c, c->cur, 1 - c->cur);
             c->cur = 1 - c->cur;

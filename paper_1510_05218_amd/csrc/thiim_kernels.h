@@ -27,6 +27,8 @@ hipError_t launch_naive(const double2* C, double2* F, const Geo& g, int kchunk,
                         hipStream_t s);
 hipError_t launch_fused(const double2* C, const double2* A, double2* B, const Geo& g,
                         int tile_x, int tile_y, int kchunk, hipStream_t s);
+hipError_t launch_blocked(const double2* C, const double2* A, double2* B, const Geo& g,
+                          int T, int ry, int kchunk, hipStream_t s);
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
                         double* part, int nblk, double* out, hipStream_t s);
 hipError_t launch_fill_zero(double2* p, long long n, hipStream_t s);

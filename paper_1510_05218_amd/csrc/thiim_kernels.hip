@@ -41,6 +41,27 @@ __device__ __forceinline__ bool resolve_xy(const Geo& g, int& i, int& j) {
     return true;
 }
 
+// Sweep grids are 1-D over tiles (x fastest, then y, then z chunk).  The
+// dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD
+// has its own L2.  tile_of() maps the dispatch index so that XCD x receives
+// the x-th contiguous range of tiles: tiles whose halos overlap then share an
+// L2 and run at about the same time.  (A bijection for any tile count.)
+struct Tile {
+    int bx, by, bz;
+};
+__device__ __forceinline__ Tile tile_of(int ntx, int nty, int ntz) {
+    const int n = ntx * nty * ntz;
+    const int lin = blockIdx.x;
+    const int q = n / 8, r = n % 8;
+    const int xcd = lin % 8, local = lin / 8;
+    const int t = xcd * q + (xcd < r ? xcd : r) + local;
+    Tile T;
+    T.bx = t % ntx;
+    T.by = (t / ntx) % nty;
+    T.bz = t / (ntx * nty);
+    return T;
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -127,29 +148,57 @@ __global__ void k_coeffs(CoefArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// helpers loading the six split parts of one cell and forming sums
+// Addressing: every access is (uniform base of array q at plane k) + (32-bit
+// in-plane byte offset of the thread's cell).  The base lives in scalar
+// registers and the offset in one vector register, so the loads use the
+// scalar-base + vector-offset form instead of one 64-bit vector pointer per
+// array (40 arrays would otherwise pin 80 VGPRs across the z loop).  A plane
+// holds at most 2^28 cells, so its byte offsets fit in 32 bits.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load6(const double2* __restrict__ base, long long S,
-                                      long long p, double2 v[6]) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) v[q] = base[q * S + p];
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource over one plane of one array: base address in SGPRs,
+// no stride, 4 GiB range (dword 3 = 0x00020000 for the gfx9 family).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double2* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(base), (short)0, -1,
+                                             0x00020000);
 }
-__device__ __forceinline__ void store6(double2* __restrict__ base, long long S,
-                                       long long p, const double2 v[6]) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) base[q * S + p] = v[q];
+__device__ __forceinline__ double2 ldo(const double2* __restrict__ b, uint32_t boff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(plane_rsrc(b), boff, 0, 0);
+    return __builtin_bit_cast(double2, v);
 }
-// coefficients t, c of six parts starting at part q0, and two Src values
+__device__ __forceinline__ void sto(double2* __restrict__ b, uint32_t boff, double2 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), plane_rsrc(b), boff,
+                                           0, 0);
+}
+// six split parts q0..q0+5 of the field buffer F at plane offset po
+__device__ __forceinline__ void load6(const double2* __restrict__ F, long long S,
+                                      long long po, uint32_t boff, double2 v[6]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = ldo(F + q * S + po, boff);
+}
+__device__ __forceinline__ void store6(double2* __restrict__ F, long long S, long long po,
+                                       uint32_t boff, const double2 v[6]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sto(F + q * S + po, boff, v[q]);
+}
+// sum of the split pair (q, q+1) of F at plane offset po
+__device__ __forceinline__ double2 pair_sum(const double2* __restrict__ F, long long S,
+                                            int q, long long po, uint32_t boff) {
+    return cadd(ldo(F + q * S + po, boff), ldo(F + (q + 1) * S + po, boff));
+}
+// coefficients t, c of the six parts starting at q0 and the two Src values
 __device__ __forceinline__ void load_coef6(const double2* __restrict__ C, long long S,
-                                           long long p, int q0, int s0, double2 t[6],
-                                           double2 c[6], double2& sa, double2& sb) {
+                                           long long po, uint32_t boff, int q0, int s0,
+                                           double2 t[6], double2 c[6], double2& sa,
+                                           double2& sb) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        t[q] = C[(q0 + q) * S + p];
-        c[q] = C[(12 + q0 + q) * S + p];
+        t[q] = ldo(C + (q0 + q) * S + po, boff);
+        c[q] = ldo(C + (12 + q0 + q) * S + po, boff);
     }
-    sa = C[s0 * S + p];
-    sb = C[(s0 + 1) * S + p];
+    sa = ldo(C + s0 * S + po, boff);
+    sb = ldo(C + (s0 + 1) * S + po, boff);
 }
 
 // ---------------------------------------------------------------------------
@@ -160,53 +209,46 @@ __device__ __forceinline__ void load_coef6(const double2* __restrict__ C, long l
 __global__ __launch_bounds__(256) void k_naive_h(const double2* __restrict__ C,
                                                  double2* __restrict__ F, Geo g,
                                                  int kchunk) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
+    const Tile T = tile_of((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kchunk - 1) / kchunk);
+    const int i = T.bx * 64 + threadIdx.x;
+    const int j = T.by * 4 + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    const int k0 = blockIdx.z * kchunk;
+    const int k0 = T.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
-    int im = i - 1, jm_i = i, jm = j - 1, im_j = j;
+    int im = i - 1, im_j = j, jm_i = i, jm = j - 1;
     const bool has_xm = resolve_xy(g, im, im_j);
     const bool has_ym = resolve_xy(g, jm_i, jm);
     const long long S = g.S;
+    const long long plane = (long long)g.nx * g.ny;
+    const uint32_t bo = 16u * (uint32_t)(j * g.nx + i);
+    const uint32_t bxm = has_xm ? 16u * (uint32_t)(im_j * g.nx + im) : 0u;
+    const uint32_t bym = has_ym ? 16u * (uint32_t)(jm * g.nx + jm_i) : 0u;
     const double2* E = F + 6 * S;
     double2 ex_zm = czero(), ey_zm = czero();
     if (k0 > 0) {
-        const long long q = cell(g, k0 - 1, j, i);
-        ex_zm = cadd(E[0 * S + q], E[1 * S + q]);
-        ey_zm = cadd(E[2 * S + q], E[3 * S + q]);
+        const long long po = (k0 - 1) * plane;
+        ex_zm = pair_sum(E, S, 0, po, bo);
+        ey_zm = pair_sum(E, S, 2, po, bo);
     }
     for (int k = k0; k < k1; ++k) {
-        const long long p = cell(g, k, j, i);
+        const long long po = k * plane;
         double2 ev[6];
-        load6(E, S, p, ev);
+        load6(E, S, po, bo, ev);
         ENbr nb;
         nb.ex = cadd(ev[0], ev[1]);
         nb.ey = cadd(ev[2], ev[3]);
         nb.ez = cadd(ev[4], ev[5]);
         nb.ex_zm = ex_zm;
         nb.ey_zm = ey_zm;
-        if (has_ym) {
-            const long long q = cell(g, k, jm, jm_i);
-            nb.ex_ym = cadd(E[0 * S + q], E[1 * S + q]);
-            nb.ez_ym = cadd(E[4 * S + q], E[5 * S + q]);
-        } else {
-            nb.ex_ym = czero();
-            nb.ez_ym = czero();
-        }
-        if (has_xm) {
-            const long long q = cell(g, k, im_j, im);
-            nb.ey_xm = cadd(E[2 * S + q], E[3 * S + q]);
-            nb.ez_xm = cadd(E[4 * S + q], E[5 * S + q]);
-        } else {
-            nb.ey_xm = czero();
-            nb.ez_xm = czero();
-        }
+        nb.ex_ym = has_ym ? pair_sum(E, S, 0, po, bym) : czero();
+        nb.ez_ym = has_ym ? pair_sum(E, S, 4, po, bym) : czero();
+        nb.ey_xm = has_xm ? pair_sum(E, S, 2, po, bxm) : czero();
+        nb.ez_xm = has_xm ? pair_sum(E, S, 4, po, bxm) : czero();
         double2 h[6], t[6], c[6], sa, sb;
-        load6(F, S, p, h);
-        load_coef6(C, S, p, 0, SRC_HXY, t, c, sa, sb);
+        load6(F, S, po, bo, h);
+        load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
         update_h(h, t, c, sa, sb, nb);
-        store6(F, S, p, h);
+        store6(F, S, po, bo, h);
         ex_zm = nb.ex;
         ey_zm = nb.ey;
     }
@@ -219,54 +261,47 @@ __global__ __launch_bounds__(256) void k_naive_h(const double2* __restrict__ C,
 __global__ __launch_bounds__(256) void k_naive_e(const double2* __restrict__ C,
                                                  double2* __restrict__ F, Geo g,
                                                  int kchunk) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
+    const Tile T = tile_of((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kchunk - 1) / kchunk);
+    const int i = T.bx * 64 + threadIdx.x;
+    const int j = T.by * 4 + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    const int k0 = blockIdx.z * kchunk;
+    const int k0 = T.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
-    int ip = i + 1, ip_j = j, jp = j + 1, jp_i = i;
+    int ip = i + 1, ip_j = j, jp_i = i, jp = j + 1;
     const bool has_xp = resolve_xy(g, ip, ip_j);
     const bool has_yp = resolve_xy(g, jp_i, jp);
     const long long S = g.S;
+    const long long plane = (long long)g.nx * g.ny;
+    const uint32_t bo = 16u * (uint32_t)(j * g.nx + i);
+    const uint32_t bxp = has_xp ? 16u * (uint32_t)(ip_j * g.nx + ip) : 0u;
+    const uint32_t byp = has_yp ? 16u * (uint32_t)(jp * g.nx + jp_i) : 0u;
     const double2* H = F;
     double2* E = F + 6 * S;
     double2 hx_zp = czero(), hy_zp = czero();
     if (k1 < g.nz) {
-        const long long q = cell(g, k1, j, i);
-        hx_zp = cadd(H[0 * S + q], H[1 * S + q]);
-        hy_zp = cadd(H[2 * S + q], H[3 * S + q]);
+        const long long po = k1 * plane;
+        hx_zp = pair_sum(H, S, 0, po, bo);
+        hy_zp = pair_sum(H, S, 2, po, bo);
     }
     for (int k = k1 - 1; k >= k0; --k) {
-        const long long p = cell(g, k, j, i);
+        const long long po = k * plane;
         double2 hv[6];
-        load6(H, S, p, hv);
+        load6(H, S, po, bo, hv);
         HNbr nb;
         nb.hx = cadd(hv[0], hv[1]);
         nb.hy = cadd(hv[2], hv[3]);
         nb.hz = cadd(hv[4], hv[5]);
         nb.hx_zp = hx_zp;
         nb.hy_zp = hy_zp;
-        if (has_yp) {
-            const long long q = cell(g, k, jp, jp_i);
-            nb.hx_yp = cadd(H[0 * S + q], H[1 * S + q]);
-            nb.hz_yp = cadd(H[4 * S + q], H[5 * S + q]);
-        } else {
-            nb.hx_yp = czero();
-            nb.hz_yp = czero();
-        }
-        if (has_xp) {
-            const long long q = cell(g, k, ip_j, ip);
-            nb.hy_xp = cadd(H[2 * S + q], H[3 * S + q]);
-            nb.hz_xp = cadd(H[4 * S + q], H[5 * S + q]);
-        } else {
-            nb.hy_xp = czero();
-            nb.hz_xp = czero();
-        }
+        nb.hx_yp = has_yp ? pair_sum(H, S, 0, po, byp) : czero();
+        nb.hz_yp = has_yp ? pair_sum(H, S, 4, po, byp) : czero();
+        nb.hy_xp = has_xp ? pair_sum(H, S, 2, po, bxp) : czero();
+        nb.hz_xp = has_xp ? pair_sum(H, S, 4, po, bxp) : czero();
         double2 e[6], t[6], c[6], sa, sb;
-        load6(E, S, p, e);
-        load_coef6(C, S, p, 6, SRC_EXY, t, c, sa, sb);
+        load6(E, S, po, bo, e);
+        load_coef6(C, S, po, bo, 6, SRC_EXY, t, c, sa, sb);
         update_e(e, t, c, sa, sb, nb);
-        store6(E, S, p, e);
+        store6(E, S, po, bo, e);
         hx_zp = nb.hx;
         hy_zp = nb.hy;
     }
@@ -305,9 +340,12 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
 
     const long long S = g.S;
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int k0 = blockIdx.z * kchunk;
+    const Tile T = tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
+                           (g.nz + kchunk - 1) / kchunk);
+    const int i0 = T.bx * TX, j0 = T.by * TY;
+    const int k0 = T.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
+    const long long plane = (long long)g.nx * g.ny;
 
     // own cell
     const int oi = tid % TX, oj = tid / TX;
@@ -316,7 +354,7 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
     int gi = i0 + oi, gj = j0 + oj;
     const bool own_store = gi < g.nx && gj < g.ny;
     const bool own_valid = resolve_xy(g, gi, gj);
-    const long long pxy = (long long)gj * g.nx + gi;
+    const uint32_t bo = own_valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
 
     // halo cell (local coordinates), H halo first
     int li = 0, lj = 0;
@@ -330,8 +368,7 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
     const int hh = lj * HW + li;  // valid only if has_hh
     int hgi = i0 + li, hgj = j0 + lj;
     const bool halo_valid = has_eh && resolve_xy(g, hgi, hgj);
-    const long long hxy = (long long)hgj * g.nx + hgi;
-    const long long plane = (long long)g.nx * g.ny;
+    const uint32_t bh = halo_valid ? 16u * (uint32_t)(hgj * g.nx + hgi) : 0u;
 
     const double2* AE = A + 6 * S;
     double2* BE = B + 6 * S;
@@ -343,36 +380,33 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
 #pragma unroll
     for (int q = 0; q < 6; ++q) eprev[q] = czero();
     if (k0 > 0) {
-        if (own_valid) load6(AE, S, (k0 - 1) * plane + pxy, eprev);
+        const long long po = (k0 - 1) * plane;
+        if (own_valid) load6(AE, S, po, bo, eprev);
         if (has_hh && halo_valid) {
-            const long long q = (k0 - 1) * plane + hxy;
-            halo_exm = cadd(AE[0 * S + q], AE[1 * S + q]);
-            halo_eym = cadd(AE[2 * S + q], AE[3 * S + q]);
+            halo_exm = pair_sum(AE, S, 0, po, bh);
+            halo_eym = pair_sum(AE, S, 2, po, bh);
         }
     }
 
     for (int k = k0; k <= k1; ++k) {
         const bool plane_in = k < g.nz;
+        const long long po = k * plane;
         double2 ecur[6];
         double2 halo_ex = czero(), halo_ey = czero();
         // ---- phase 1: E^n(k) sums into LDS
-        if (plane_in) {
-            if (own_valid) {
-                load6(AE, S, k * plane + pxy, ecur);
-            } else {
 #pragma unroll
-                for (int q = 0; q < 6; ++q) ecur[q] = czero();
-            }
+        for (int q = 0; q < 6; ++q) ecur[q] = czero();
+        if (plane_in) {
+            if (own_valid) load6(AE, S, po, bo, ecur);
             Es[0][eo] = cadd(ecur[0], ecur[1]);
             Es[1][eo] = cadd(ecur[2], ecur[3]);
             Es[2][eo] = cadd(ecur[4], ecur[5]);
             if (has_eh) {
                 double2 ex = czero(), ey = czero(), ez = czero();
                 if (halo_valid) {
-                    const long long q = k * plane + hxy;
-                    ex = cadd(AE[0 * S + q], AE[1 * S + q]);
-                    ey = cadd(AE[2 * S + q], AE[3 * S + q]);
-                    ez = cadd(AE[4 * S + q], AE[5 * S + q]);
+                    ex = pair_sum(AE, S, 0, po, bh);
+                    ey = pair_sum(AE, S, 2, po, bh);
+                    ez = pair_sum(AE, S, 4, po, bh);
                 }
                 Es[0][eh] = ex;
                 Es[1][eh] = ey;
@@ -380,9 +414,6 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
                 halo_ex = ex;
                 halo_ey = ey;
             }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) ecur[q] = czero();
         }
         __syncthreads();
         // ---- phase 2: H^{n+1/2}(k)
@@ -400,12 +431,11 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
                 nb.ez_ym = Es[2][eo - EW];
                 nb.ey_xm = Es[1][eo - 1];
                 nb.ez_xm = Es[2][eo - 1];
-                const long long p = k * plane + pxy;
                 double2 h[6], t[6], c[6], sa, sb;
-                load6(A, S, p, h);
-                load_coef6(C, S, p, 0, SRC_HXY, t, c, sa, sb);
+                load6(A, S, po, bo, h);
+                load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
-                if (own_store && k < k1) store6(B, S, p, h);
+                if (own_store && k < k1) store6(B, S, po, bo, h);
                 hx = cadd(h[0], h[1]);
                 hy = cadd(h[2], h[3]);
                 hz = cadd(h[4], h[5]);
@@ -421,10 +451,9 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
                 nb.ez_ym = Es[2][eh - EW];
                 nb.ey_xm = Es[1][eh - 1];
                 nb.ez_xm = Es[2][eh - 1];
-                const long long p = k * plane + hxy;
                 double2 h[6], t[6], c[6], sa, sb;
-                load6(A, S, p, h);
-                load_coef6(C, S, p, 0, SRC_HXY, t, c, sa, sb);
+                load6(A, S, po, bh, h);
+                load_coef6(C, S, po, bh, 0, SRC_HXY, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
                 hhx = cadd(h[0], h[1]);
                 hhy = cadd(h[2], h[3]);
@@ -443,11 +472,11 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
             nb.hz_yp = Hs[2][ho + HW];
             nb.hy_xp = Hs[1][ho + 1];
             nb.hz_xp = Hs[2][ho + 1];
-            const long long p = (k - 1) * plane + pxy;
+            const long long pm = po - plane;
             double2 t[6], c[6], sa, sb;
-            load_coef6(C, S, p, 6, SRC_EXY, t, c, sa, sb);
+            load_coef6(C, S, pm, bo, 6, SRC_EXY, t, c, sa, sb);
             update_e(eprev, t, c, sa, sb, nb);
-            if (own_store) store6(BE, S, p, eprev);
+            if (own_store) store6(BE, S, pm, bo, eprev);
         }
         __syncthreads();
         // ---- phase 4: H sums of plane k into LDS, shift the z state
@@ -466,6 +495,191 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
         halo_eym = halo_ey;
 #pragma unroll
         for (int q = 0; q < 6; ++q) eprev[q] = ecur[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Temporally blocked pass: T THIIM iterations per HBM pass, A -> B.
+//
+// A workgroup covers a region of 64 x RY columns (one wavefront per row,
+// lanes along x) and streams z.  Each thread keeps one column for the whole
+// stream and for all T stages (fixed execution to data): the stage outputs it
+// needs one plane later -- old values and z-neighbour sums -- stay in its
+// registers, and the x/y-neighbour sums of every stage pass through LDS.
+// At step k stage s updates H_s at plane k-s+1 and E_s at plane k-s, so one
+// HBM read of plane k feeds all T stages (GPU form of the wavefront in z).
+// Only the centre (64-2T) x (RY-2T) columns are valid after T stages; they
+// are stored, the ring is recomputed by the neighbouring workgroups.  Region
+// cells beyond the ring read clamped neighbours: their (unused) results
+// never reach a stored cell.  z chunks overlap by T-1 planes.
+// Coefficients of the 40-array layout are re-read for every stage.
+// ---------------------------------------------------------------------------
+template <int RY, int T>
+__global__ __launch_bounds__(64 * RY) void k_blocked(const double2* __restrict__ C,
+                                                     const double2* __restrict__ A,
+                                                     double2* __restrict__ B, Geo g,
+                                                     int kchunk) {
+    constexpr int R = 64 * RY;
+    constexpr int OX = 64 - 2 * T, OY = RY - 2 * T;  // stored tile
+    static_assert(OY >= 1, "region too small for T stages");
+    __shared__ double2 LE[T][3][R];     // E_{s} sums, s = 0..T-1 (current plane)
+    __shared__ double2 LH[T][2][3][R];  // H_{s+1} sums, by step parity
+
+    const long long S = g.S;
+    const long long plane = (long long)g.nx * g.ny;
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+    const Tile TT = tile_of((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
+                            (g.nz + kchunk - 1) / kchunk);
+    const int ux = TT.bx * OX - T + lane;  // unwrapped global column
+    const int uy = TT.by * OY - T + row;
+    int gi = ux, gj = uy;
+    const bool valid = resolve_xy(g, gi, gj);
+    const bool own = lane >= T && lane < 64 - T && row >= T && row < RY - T &&
+                     ux < g.nx && uy < g.ny;
+    const uint32_t bo = valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
+    const int me = row * 64 + lane;
+    const int xm = row * 64 + (lane > 0 ? lane - 1 : 0);
+    const int xp = row * 64 + (lane < 63 ? lane + 1 : 63);
+    const int ym = (row > 0 ? row - 1 : 0) * 64 + lane;
+    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * 64 + lane;
+
+    const int k0 = TT.bz * kchunk;
+    const int k1 = min(g.nz, k0 + kchunk);
+    const int ks = max(0, k0 - (T - 1));
+    const int kend = min(k1 + T - 1, g.nz + T - 1);
+
+    for (int i = threadIdx.x; i < T * 3 * R; i += 64 * RY) {
+        (&LE[0][0][0])[i] = czero();
+        (&LH[0][0][0][0])[i] = czero();
+        (&LH[0][0][0][0])[i + T * 3 * R] = czero();
+    }
+
+    const double2* AE = A + 6 * S;
+    double2* BE = B + 6 * S;
+
+    // carried state
+    double2 e0p[6];            // E_0 parts at plane k-1
+    double2 hc[T][6];          // H_s parts at plane k-s (s = 1..T-1 used)
+    double2 ep[T][6];          // E_s parts at plane k-1-s (s = 1..T-1 used)
+    double2 hTx = czero(), hTy = czero(), hTz = czero();  // H_T sums, plane k-T
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        e0p[q] = czero();
+#pragma unroll
+        for (int s = 0; s < T; ++s) {
+            hc[s][q] = czero();
+            ep[s][q] = czero();
+        }
+    }
+    if (ks > 0 && valid) load6(AE, S, (ks - 1) * plane, bo, e0p);
+    __syncthreads();
+
+    for (int k = ks; k <= kend; ++k) {
+        const int par = k & 1;
+        // ---- E_0(k) sums into LDS
+        double2 e0c[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) e0c[q] = czero();
+        if (k < g.nz && valid) load6(AE, S, k * plane, bo, e0c);
+        LE[0][0][me] = cadd(e0c[0], e0c[1]);
+        LE[0][1][me] = cadd(e0c[2], e0c[3]);
+        LE[0][2][me] = cadd(e0c[4], e0c[5]);
+        __syncthreads();
+
+        double2 hn[T][6], en[T][6];
+#pragma unroll
+        for (int s = 1; s <= T; ++s) {
+            // ---- H_s at plane kh
+            const int kh = k - s + 1;
+            double2 h[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) h[q] = czero();
+            if (valid && kh >= 0 && kh < g.nz) {
+                const long long po = kh * plane;
+                // old value: H_{s-1}(kh)
+                if (s == 1) {
+                    load6(A, S, po, bo, h);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];
+                }
+                const double2* zp = (s == 1) ? e0p : ep[s - 1];  // E_{s-1}(kh-1)
+                ENbr nb;
+                nb.ex = LE[s - 1][0][me];
+                nb.ey = LE[s - 1][1][me];
+                nb.ez = LE[s - 1][2][me];
+                nb.ex_zm = cadd(zp[0], zp[1]);
+                nb.ey_zm = cadd(zp[2], zp[3]);
+                nb.ex_ym = LE[s - 1][0][ym];
+                nb.ez_ym = LE[s - 1][2][ym];
+                nb.ey_xm = LE[s - 1][1][xm];
+                nb.ez_xm = LE[s - 1][2][xm];
+                double2 t[6], c[6], sa, sb;
+                load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
+                update_h(h, t, c, sa, sb, nb);
+                if (s == T && own && kh >= k0 && kh < k1) store6(B, S, po, bo, h);
+            }
+            const double2 hx = cadd(h[0], h[1]), hy = cadd(h[2], h[3]), hz = cadd(h[4], h[5]);
+            LH[s - 1][par][0][me] = hx;
+            LH[s - 1][par][1][me] = hy;
+            LH[s - 1][par][2][me] = hz;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) hn[s - 1][q] = h[q];
+            // ---- E_s at plane ke (old value E_{s-1}(ke))
+            const int ke = k - s;
+            double2 e[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) e[q] = czero();
+            if (valid && ke >= 0 && ke < g.nz) {
+                const long long po = ke * plane;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) e[q] = (s == 1) ? e0p[q] : ep[s - 1][q];
+                HNbr nb;
+                if (s == T) {
+                    nb.hx = hTx;
+                    nb.hy = hTy;
+                    nb.hz = hTz;
+                } else {
+                    nb.hx = cadd(hc[s][0], hc[s][1]);
+                    nb.hy = cadd(hc[s][2], hc[s][3]);
+                    nb.hz = cadd(hc[s][4], hc[s][5]);
+                }
+                nb.hx_zp = hx;
+                nb.hy_zp = hy;
+                nb.hx_yp = LH[s - 1][par ^ 1][0][yp];
+                nb.hz_yp = LH[s - 1][par ^ 1][2][yp];
+                nb.hy_xp = LH[s - 1][par ^ 1][1][xp];
+                nb.hz_xp = LH[s - 1][par ^ 1][2][xp];
+                double2 t[6], c[6], sa, sb;
+                load_coef6(C, S, po, bo, 6, SRC_EXY, t, c, sa, sb);
+                update_e(e, t, c, sa, sb, nb);
+                if (s == T && own && ke >= k0 && ke < k1) store6(BE, S, po, bo, e);
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) en[s - 1][q] = e[q];
+            if (s < T) {
+                LE[s][0][me] = cadd(e[0], e[1]);
+                LE[s][1][me] = cadd(e[2], e[3]);
+                LE[s][2][me] = cadd(e[4], e[5]);
+                __syncthreads();
+            }
+            if (s == T) {
+                hTx = hx;
+                hTy = hy;
+                hTz = hz;
+            }
+        }
+        if (T == 1) __syncthreads();
+        // ---- shift the carried state one plane
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            e0p[q] = e0c[q];
+#pragma unroll
+            for (int s = 1; s < T; ++s) {
+                hc[s][q] = hn[s - 1][q];
+                ep[s][q] = en[s - 1][q];
+            }
+        }
     }
 }
 
@@ -566,7 +780,7 @@ static int nchunks(const Geo& g, int kchunk) { return (g.nz + kchunk - 1) / kchu
 
 hipError_t launch_naive(const double2* C, double2* F, const Geo& g, int kchunk,
                         hipStream_t s) {
-    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, nchunks(g, kchunk));
+    dim3 grid(((g.nx + 63) / 64) * ((g.ny + 3) / 4) * nchunks(g, kchunk));
     hipLaunchKernelGGL(k_naive_h, grid, dim3(64, 4), 0, s, C, F, g, kchunk);
     hipLaunchKernelGGL(k_naive_e, grid, dim3(64, 4), 0, s, C, F, g, kchunk);
     return hipGetLastError();
@@ -574,7 +788,8 @@ hipError_t launch_naive(const double2* C, double2* F, const Geo& g, int kchunk,
 
 hipError_t launch_fused(const double2* C, const double2* A, double2* B, const Geo& g,
                         int tile_x, int tile_y, int kchunk, hipStream_t s) {
-    dim3 grid((g.nx + tile_x - 1) / tile_x, (g.ny + tile_y - 1) / tile_y, nchunks(g, kchunk));
+    dim3 grid(((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y) *
+              nchunks(g, kchunk));
     if (tile_x == 64 && tile_y == 8)
         hipLaunchKernelGGL((k_fused<64, 8>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
     else if (tile_x == 32 && tile_y == 8)
@@ -583,6 +798,22 @@ hipError_t launch_fused(const double2* C, const double2* A, double2* B, const Ge
         hipLaunchKernelGGL((k_fused<64, 4>), grid, dim3(256), 0, s, C, A, B, g, kchunk);
     else if (tile_x == 16 && tile_y == 16)
         hipLaunchKernelGGL((k_fused<16, 16>), grid, dim3(256), 0, s, C, A, B, g, kchunk);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_blocked(const double2* C, const double2* A, double2* B, const Geo& g,
+                          int T, int ry, int kchunk, hipStream_t s) {
+    const int ox = 64 - 2 * T, oy = ry - 2 * T;
+    if (oy < 1) return hipErrorInvalidValue;
+    dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
+    if (T == 2 && ry == 8)
+        hipLaunchKernelGGL((k_blocked<8, 2>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
+    else if (T == 2 && ry == 6)
+        hipLaunchKernelGGL((k_blocked<6, 2>), grid, dim3(384), 0, s, C, A, B, g, kchunk);
+    else if (T == 1 && ry == 8)
+        hipLaunchKernelGGL((k_blocked<8, 1>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libthiim.so")
+# THIIM_LIBRARY may name another build of the same C-ABI (e.g. a tuning build)
+LIB_PATH = os.environ.get("THIIM_LIBRARY") or os.path.join(_HERE, "libthiim.so")
 
 THIIM_OK = 0
 THIIM_EINVAL = -1

@@ -59,7 +59,7 @@ def test_coefficients_match_oracle():
         assert np.all(err <= 2e-15 * np.abs(co[q]) + 1e-300), q
 
 
-@pytest.mark.parametrize("kernel", ["naive", "fused"])
+@pytest.mark.parametrize("kernel", ["naive", "fused", "blocked"])
 def test_c1_layered_textured_200_iterations(kernel):
     """24 x 24 interior cells + 2 x 6 PML planes, three textured layers,
     normal-incidence x-polarised source, 200 iterations."""
@@ -83,6 +83,11 @@ def test_random_ragged_problem(bcx, bcy):
         for zc in (0, 5, 64):
             _, xf = _gpu_run(pb, 25, kernel="fused", tile=tile, z_chunk=zc)
             assert torch.equal(xf, xn), (tile, zc)
+    # temporally blocked: 12 two-iteration passes + 1 fused remainder
+    for tile in [(64, 8), (64, 6)]:
+        for zc in (0, 3, 5, 64):
+            _, xb = _gpu_run(pb, 25, kernel="blocked", tile=tile, z_chunk=zc)
+            assert torch.equal(xb, xn), ("blocked", tile, zc)
 
 
 def test_tiny_grids_wrap_many_times():
@@ -94,15 +99,17 @@ def test_tiny_grids_wrap_many_times():
         _, xo = _oracle_run(pb, 15)
         _, xn = _gpu_run(pb, 15, kernel="naive")
         _, xf = _gpu_run(pb, 15, kernel="fused")
+        _, xb = _gpu_run(pb, 15, kernel="blocked")
         assert _rel(xn.cpu().numpy(), xo) < 1e-12
         assert torch.equal(xf, xn)
+        assert torch.equal(xb, xn)
 
 
 def test_zero_source_stays_zero():
     _require_gpu()
     pb = inputs.solar_cell(24, 20, 30, seed=2, npml=4)
     pb.sources = {}
-    for kernel in ("naive", "fused"):
+    for kernel in ("naive", "fused", "blocked"):
         _, x = _gpu_run(pb, 30, kernel=kernel)
         assert not torch.any(x != 0)
 
@@ -151,7 +158,7 @@ def test_full_size_flat_stack_512():
         pytest.skip("needs the 288 GB of an MI355X")
     n = 512
     pb = inputs.solar_cell(n, n, n, seed=3, npml=6, flat=True)
-    s = thiim.Solver(pb, kernel="fused")
+    s = thiim.Solver(pb, kernel="blocked")
     s.iterate(100)
     x = s.fields()
     small = inputs.solar_cell(2, 2, n, seed=3, npml=6, flat=True)
