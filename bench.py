@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """THIIM benchmark on one MI355X.
 
-Workload (default): the 512 x 512 x 512 production-size problem -- three
-seeded layers (eps' in [1,16], eps'' in [0,0.5]) with a textured interface
-(amplitude 4 cells), 200 SiO2-like spheres (eps = 2.1) in the last layer,
-6-plane graded PML in z, periodic x/y, normal-incidence x-polarised source,
-lambda = 600 nm at 20 nm cells -- 100 THIIM iterations in complex128.
+Workload: the 512 x 512 x 512 production-size problem -- three seeded layers
+(eps' in [1,16], eps'' in [0,0.5]) with a textured interface (amplitude 4
+cells), 200 SiO2-like spheres (eps = 2.1) in the last layer, 6-plane graded
+PML in z, periodic x/y, normal-incidence x-polarised source, lambda = 600 nm
+at 20 nm cells -- 100 THIIM iterations in complex128 (FP64).
 
-One step = the whole hot path on the resident inputs: coefficient assembly
-(thiim_create), 100 iterations (thiim_iterate) and the FP64 residual
-(thiim_residual).  The value is lattice-site updates per second (GLUP/s:
-nx*ny*nz*100 / step time).  The dominant kernel's roofline entry uses the
-average duration of one iteration launch measured with HIP events on the
-library's stream, and the algorithmic bytes of that sweep per cell update.
+One step = the whole hot path on inputs resident in HBM: coefficient
+assembly (thiim_create), 100 iterations (thiim_iterate) and the FP64
+residual (thiim_residual).  value = nx*ny*nz*100 / step time (GLUP/s).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--kernel fused]
-       [--size 512] [--iters 100] [--no-cpu-baseline]
+The headline variant is the two-iteration temporally blocked sweep on the
+compact coefficient storage; the other (kernel, storage) variants -- among
+them the naive one-sweep-per-half-step kernel on the paper's 40-array layout
+-- are timed once each for context.  All variants produce bit-identical
+iterates.  The roofline entry is for the headline sweep kernel: algorithmic
+bytes per launch / average launch time measured with HIP events on the
+library's stream; ``traffic`` comes from the committed rocprofv3 counter
+summary when it was taken on the current kernel sources, else null.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 512]
+       [--iters 100] [--kernel blocked] [--storage compact] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -28,99 +34,133 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# algorithmic HBM bytes per cell and iteration, complex128, 40-array layout
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_thiim_512cubed.json")
+
+# Algorithmic HBM bytes per cell and iteration (complex128, 16 B per value)
+# away from the source plane (Src arrays are read only where non-zero):
+#   full storage (the paper's 28 coefficient arrays):
+#     naive:   H sweep 12 t/c + 6 H + 6 E read, 6 H written = 480 B, E sweep
+#              the same -> 960 B
+#     fused:   24 t/c + 12 fields read, 12 written = 768 B
+#     blocked: one pass for 2 iterations reads 24 t/c + 12 fields and writes
+#              12 = 768 B per pass -> 384 B
+#   compact storage (eps per cell):
+#     naive:   H sweep 12 read + 6 written = 288 B, E sweep 13 + 6 = 304 B
+#     fused:   eps + 12 fields read, 12 written = 400 B
+#     blocked: 400 B per two-iteration pass -> 200 B
 BYTES_PER_LUP = {
-    "naive": 1024,   # two sweeps: (26 reads + 6 writes) x 16 B each
-    "fused": 832,    # one pass: 40 reads + 12 writes, x 16 B
-    "blocked": 416,  # one pass per two iterations: 40 reads + 12 writes, x 16 B
+    ("naive", "full"): 960, ("fused", "full"): 768, ("blocked", "full"): 384,
+    ("naive", "compact"): 592, ("fused", "compact"): 400, ("blocked", "compact"): 200,
 }
 ITERS_PER_LAUNCH = {"naive": 0.5, "fused": 1, "blocked": 2}
+SWEEP_KERNEL = {
+    ("naive", "full"): "k_naive_h<thiim::FullCoefs>",
+    ("fused", "full"): "k_fused<64, 8, thiim::FullCoefs>",
+    ("blocked", "full"): "k_blocked<64, 8, 2, thiim::FullCoefs>",
+    ("naive", "compact"): "k_naive_h<thiim::CompactCoefs>",
+    ("fused", "compact"): "k_fused<64, 8, thiim::CompactCoefs>",
+    ("blocked", "compact"): "k_blocked<32, 16, 2, thiim::CompactCoefs>",
+}
+CONTEXT_VARIANTS = [("naive", "full"), ("fused", "full"), ("naive", "compact"),
+                    ("fused", "compact")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_kernel_run(torch, thiim, pb, kernel, iters, steps, warmup, tile=(0, 0),
-                    z_chunk=0):
-    """Runs warmup + steps whole-job steps; returns timings."""
+def run_steps(torch, thiim, pb, kernel, storage, iters, steps, warmup):
+    """warmup + steps whole-job steps; returns per-step wall ms, per-iteration
+    sweep ms (HIP events around thiim_iterate on the library's stream) and the
+    final residual."""
     stream = torch.cuda.current_stream()
     step_ms, iter_ms, res = [], [], None
     for s in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        solver = thiim.Solver(pb, kernel=kernel, tile=tile, z_chunk=z_chunk,
-                              stream=stream)
+        solver = thiim.Solver(pb, kernel=kernel, storage=storage, stream=stream)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         solver.iterate(iters)
         ev1.record(stream)
-        res = solver.residual()       # synchronising
+        res = solver.residual()  # synchronising
         t1 = time.perf_counter()
         solver.close()
+        sweep = ev0.elapsed_time(ev1) / iters
         if s >= warmup:
             step_ms.append((t1 - t0) * 1e3)
-            iter_ms.append(ev0.elapsed_time(ev1) / iters)
-        log(f"[bench] {kernel} step {s} ({'warmup' if s < warmup else 'timed'}): "
-            f"{(t1 - t0) * 1e3:.1f} ms, {ev0.elapsed_time(ev1) / iters:.3f} ms/iteration, "
-            f"residual {res:.3e}")
+            iter_ms.append(sweep)
+        log(f"[bench] {kernel}/{storage} step {s} ({'warmup' if s < warmup else 'timed'}): "
+            f"{(t1 - t0) * 1e3:.1f} ms, {sweep:.3f} ms/iteration, residual {res:.3e}")
     return step_ms, iter_ms, res
 
 
 def cpu_baseline(pb_full, budget_s=15.0):
-    """The CPU oracle on a bounded sample of the same workload: the first
-    planes of the 512^3 geometry (PML, source, first layer) as their own grid,
-    iterated on all host cores."""
+    """The CPU oracle on a bounded sample of the same workload: its first 24
+    planes (PML, source, first layer) as a grid of their own, iterated on all
+    host cores."""
     import numpy as np
 
     import oracle
-    from paper_1510_05218_amd import inputs
 
     nzs = 24
     eps = np.ascontiguousarray(pb_full.eps[:nzs])
     src = {k: np.ascontiguousarray(v[:nzs]) for k, v in pb_full.sources.items()}
-    sig_e = pb_full.sig_e[:nzs].copy()
-    sig_h = pb_full.sig_h[:nzs].copy()
-    coef = oracle.coeffs(eps, sig_e, sig_h, src, pb_full.omega, pb_full.tau)
+    coef = oracle.coeffs(eps, pb_full.sig_e[:nzs].copy(), pb_full.sig_h[:nzs].copy(), src,
+                         pb_full.omega, pb_full.tau)
     x = oracle.zero_fields(eps.shape)
     t = time.perf_counter()
     oracle.iterate(coef, x, 1)
     one = time.perf_counter() - t
-    n = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    n = max(1, min(1000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
     oracle.iterate(coef, x, n)
     dt = time.perf_counter() - t
-    cells = eps.size
-    del inputs
     return {
-        "value": cells * n / dt / 1e9,
+        "value": eps.size * n / dt / 1e9,
         "unit": "GLUP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"{eps.shape[2]}x{eps.shape[1]}x{nzs} leading planes of the "
-                  f"workload, {n} iterations, {dt:.1f} s",
+        "sample": f"{eps.shape[2]}x{eps.shape[1]}x{nzs} leading planes of the workload "
+                  f"(28-array layout, C, OpenMP), {n} iterations in {dt:.1f} s",
     }
+
+
+def traffic_for(kernel_name, n_cells):
+    """Counter traffic (bytes per launch) if the committed summary matches
+    the current kernel sources and grid, else None."""
+    from paper_1510_05218_amd import profiling
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != profiling.source_hash() or t.get("cells") != n_cells:
+        return None
+    k = t["kernels"].get(kernel_name)
+    return None if k is None else k["bytes_per_launch"]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kernel", default="blocked", choices=["naive", "fused", "blocked"])
+    ap.add_argument("--storage", default="compact", choices=["full", "compact"])
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--iters", type=int, default=100)
-    ap.add_argument("--compare", default="fused,naive",
-                    help="comma list of extra kernels timed for context")
+    ap.add_argument("--no-context", action="store_true", help="skip the context variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        sys.exit("bench.py: this THIIM build runs on one GPU only; the multi-GPU "
-                 "(z-slab) decomposition is a design note, not implemented.")
+        sys.exit("bench.py: this THIIM build runs on one GPU only; the z-slab multi-GPU "
+                 "decomposition is described in the design notes, not implemented.")
 
     import torch
 
@@ -130,10 +170,9 @@ def main():
         sys.exit("bench.py needs an MI355X GPU")
     thiim.lib()
     n = args.size
-    log(f"[bench] generating {n}^3 workload")
+    log(f"[bench] generating the {n}^3 workload")
     pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200 if n >= 128 else 0)
     N = n ** 3
-    # inputs resident in HBM before any timed region
     dev = inputs.Problem(**{**pb.__dict__})
     dev.eps = torch.from_numpy(pb.eps).cuda()
     dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
@@ -149,29 +188,36 @@ def main():
         del a, b
         torch.cuda.empty_cache()
 
-    results = {}
-    for kernel in [args.kernel] + [k for k in args.compare.split(",") if k and k != args.kernel]:
-        step_ms, iter_ms, res = time_kernel_run(torch, thiim, dev, kernel, args.iters,
-                                                args.steps if kernel == args.kernel else 1,
-                                                args.warmup if kernel == args.kernel else 1)
-        results[kernel] = (step_ms, iter_ms, res)
-        torch.cuda.empty_cache()
+    head = (args.kernel, args.storage)
+    results = {head: run_steps(torch, thiim, dev, args.kernel, args.storage, args.iters,
+                               args.steps, args.warmup)}
+    torch.cuda.empty_cache()
+    if not args.no_context:
+        for v in CONTEXT_VARIANTS:
+            if v != head:
+                results[v] = run_steps(torch, thiim, dev, v[0], v[1], args.iters, 1, 0)
+                torch.cuda.empty_cache()
 
-    step_ms, iter_ms, res = results[args.kernel]
+    step_ms, iter_ms, res = results[head]
     ms_per_step = sum(step_ms) / len(step_ms)
     it_ms = sum(iter_ms) / len(iter_ms)
     glups = N * args.iters / (ms_per_step * 1e-3) / 1e9
-    # dominant kernel: the sweep (two launches per iteration for naive, one per
-    # iteration for fused, one per two iterations for blocked)
     ipl = ITERS_PER_LAUNCH[args.kernel]
-    bytes_per_launch = BYTES_PER_LUP[args.kernel] * N * ipl
-    achieved = bytes_per_launch / (it_ms * ipl * 1e-3) / 1e9
-    extra = {}
-    for k, (sm, im, r) in results.items():
-        extra[k] = {"ms_per_iteration": sum(im) / len(im),
-                    "sweep_glups": N / (sum(im) / len(im) * 1e-3) / 1e9,
-                    "alg_bytes_per_lup": BYTES_PER_LUP[k],
-                    "final_rel_residual": r}
+    launch_ms = it_ms * ipl
+    bytes_per_launch = BYTES_PER_LUP[head] * N * ipl
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    traffic = traffic_for(SWEEP_KERNEL[head], N)
+    kernels = {}
+    for (k, st), (sm, im, r) in results.items():
+        ms = sum(im) / len(im)
+        kernels[f"{k}/{st}"] = {
+            "sweep_kernel": SWEEP_KERNEL[(k, st)],
+            "ms_per_iteration": ms,
+            "sweep_glups": N / (ms * 1e-3) / 1e9,
+            "alg_bytes_per_lup": BYTES_PER_LUP[(k, st)],
+            "alg_gbs": BYTES_PER_LUP[(k, st)] * N / (ms * 1e-3) / 1e9,
+            "final_rel_residual": r,
+        }
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -191,11 +237,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"thiim_{n}x{n}x{n}_layered_textured_spheres_pml6",
                    "iterations": args.iters, "kernel": args.kernel,
-                   "precision": "fp64 complex"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                   "storage": args.storage, "precision": "fp64 complex"},
+        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL[head], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms},
         "cpu_baseline": cpu,
-        "kernels": extra,
+        "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
 

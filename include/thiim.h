@@ -63,6 +63,14 @@ extern "C" {
 #define THIIM_KERNEL_FUSED 2   /* H and E half-steps in one HBM pass */
 #define THIIM_KERNEL_BLOCKED 3 /* t_block iterations per HBM pass */
 
+/* Coefficient storage (both give bit-identical iterates). */
+#define THIIM_STORAGE_FULL 0    /* the 28 coefficient arrays of the paper's
+                                 * layout (40 double-complex arrays per cell
+                                 * with the 12 fields) */
+#define THIIM_STORAGE_COMPACT 1 /* per-cell eps and the 4 Src arrays; t and c
+                                 * derived in the sweeps from eps and per-plane
+                                 * tables by the same formulas */
+
 typedef struct thiim_ctx thiim_ctx;
 
 typedef struct {
@@ -74,9 +82,10 @@ typedef struct {
     int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED: 0 (auto,
                        * = 2), 1 or 2; a remainder runs through the fused sweep */
     int tile_x, tile_y; /* fused sweep: tile 64x8, 32x8, 64x4 or 16x16; blocked
-                         * sweep: region 64x8 or 64x6 (columns x rows) of which
-                         * the centre (64-2T) x (rows-2T) is stored; 0x0 = auto */
+                         * sweep: region 64x8, 64x6 or 32x16 (columns x rows) of
+                         * which the centre (x-2T) x (y-2T) is stored; 0x0 = auto */
     int z_chunk;      /* z planes per workgroup stream (0 = auto) */
+    int storage;      /* THIIM_STORAGE_FULL or THIIM_STORAGE_COMPACT */
     void *stream;     /* hipStream_t */
 } thiim_grid;
 
@@ -99,8 +108,9 @@ typedef struct {
     const double *src[4];
 } thiim_coeffs;
 
-/* Bytes of device workspace a context on this grid needs (28 coefficient
- * arrays, two 12-array field buffers, reduction scratch; 256-B aligned). */
+/* Bytes of device workspace a context on this grid needs: the coefficient
+ * data (full: 28 arrays; compact: 5 arrays), two 12-array field buffers,
+ * per-plane tables and reduction scratch; 256-byte aligned. */
 int thiim_workspace_bytes(const thiim_grid *g, size_t *bytes);
 
 /* Validates the inputs, builds the 28 coefficient arrays on the device
@@ -131,7 +141,8 @@ int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
 int thiim_get_fields(thiim_ctx *ctx, double *dst);
 int thiim_set_fields(thiim_ctx *ctx, const double *src);
 
-/* Device copy of the 28 coefficient arrays (28*2*N doubles).  Synchronising. */
+/* Device copy of the 28 coefficient arrays (28*2*N doubles), expanded from
+ * the compact storage when that is in use.  Synchronising. */
 int thiim_get_coeffs(thiim_ctx *ctx, double *dst);
 
 /* Iterations done since create / set_fields. */

@@ -32,10 +32,12 @@ constexpr size_t kHeaderBytes = 4096;  // flag, reduction output
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    long long N, S;  // cells, array stride (double2)
-    size_t off_sig;  // 2*nz doubles
-    size_t off_part; // 2*kResidBlocks doubles
-    size_t off_coef, off_a, off_b;
+    long long N, S;   // cells, array stride (double2)
+    size_t off_sig;   // 2*nz doubles
+    size_t off_part;  // 2*kResidBlocks doubles
+    size_t off_plane; // nz PlaneCoef
+    size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
+    size_t off_a, off_b;
     size_t total;
 };
 
@@ -48,8 +50,10 @@ Layout layout_of(const thiim_grid* g) {
     off = align_up(off + 2 * sizeof(double) * g->nz, kAlign);
     L.off_part = off;
     off = align_up(off + 2 * sizeof(double) * kResidBlocks, kAlign);
+    L.off_plane = off;
+    off = align_up(off + sizeof(thiim::PlaneCoef) * g->nz, kAlign);
     L.off_coef = off;
-    off += (size_t)28 * L.S * 16;
+    off += (size_t)(g->storage == THIIM_STORAGE_COMPACT ? 5 : 28) * L.S * 16;
     L.off_a = off;
     off += (size_t)12 * L.S * 16;
     L.off_b = off;
@@ -73,12 +77,17 @@ int check_grid(const thiim_grid* g) {
     if (g->kernel < THIIM_KERNEL_AUTO || g->kernel > THIIM_KERNEL_BLOCKED)
         return fail(THIIM_EINVAL, "unknown kernel");
     if (g->t_block < 0 || g->t_block > 2) return fail(THIIM_EINVAL, "t_block must be 0 (auto), 1 or 2");
+    if (g->storage != THIIM_STORAGE_FULL && g->storage != THIIM_STORAGE_COMPACT)
+        return fail(THIIM_EINVAL, "storage must be FULL or COMPACT");
+    if ((long long)g->nx * g->ny * 16 > 0xFFFFFFFFLL)
+        return fail(THIIM_EINVAL, "an x-y plane must hold fewer than 2^28 cells");
     if (g->z_chunk < 0) return fail(THIIM_EINVAL, "z_chunk must be >= 0");
     const bool tile_auto = g->tile_x == 0 && g->tile_y == 0;
     if (g->kernel == THIIM_KERNEL_BLOCKED) {
-        if (!tile_auto && !(g->tile_x == 64 && (g->tile_y == 8 || g->tile_y == 6)))
-            return fail(THIIM_EINVAL, "blocked kernel: tile must be 0x0 (auto), 64x8 or 64x6 "
-                                      "(region columns x rows)");
+        if (!tile_auto && !(g->tile_x == 64 && (g->tile_y == 8 || g->tile_y == 6)) &&
+            !(g->tile_x == 32 && g->tile_y == 16))
+            return fail(THIIM_EINVAL, "blocked kernel: tile must be 0x0 (auto), 64x8, 64x6 or "
+                                      "32x16 (region columns x rows)");
     } else {
         const bool tile_ok = (g->tile_x == 64 && g->tile_y == 8) ||
                              (g->tile_x == 32 && g->tile_y == 8) ||
@@ -96,6 +105,7 @@ struct thiim_ctx {
     thiim_grid g;
     Geo geo;
     Layout L;
+    thiim::CoefView cv;
     double omega;
     hipStream_t stream;
     int device;
@@ -111,7 +121,7 @@ struct thiim_ctx {
     long long iters;
     int kernel;  // resolved THIIM_KERNEL_*
     int tile_x, tile_y, z_chunk;      // fused sweep
-    int t_block, region_y, bz_chunk;  // blocked sweep
+    int t_block, region_x, region_y, bz_chunk;  // blocked sweep
 };
 
 namespace {
@@ -126,7 +136,13 @@ int auto_chunk(const thiim_grid& g, long long tiles) {
 
 int resolve_tiles(thiim_ctx* c) {
     const thiim_grid& g = c->g;
-    c->kernel = g.kernel == THIIM_KERNEL_AUTO ? THIIM_KERNEL_FUSED : g.kernel;
+    // auto: the two-iteration blocked sweep when the coefficients are compact
+    // (its second stage then re-reads 16 B per cell), the fused sweep for the
+    // 28-array layout (where the second stage would re-read 448 B per cell)
+    if (g.kernel == THIIM_KERNEL_AUTO)
+        c->kernel = g.storage == THIIM_STORAGE_COMPACT ? THIIM_KERNEL_BLOCKED : THIIM_KERNEL_FUSED;
+    else
+        c->kernel = g.kernel;
     if (c->kernel != THIIM_KERNEL_BLOCKED && g.tile_x != 0) {
         c->tile_x = g.tile_x;
         c->tile_y = g.tile_y;
@@ -144,8 +160,11 @@ int resolve_tiles(thiim_ctx* c) {
                             ((g.ny + c->tile_y - 1) / c->tile_y);
     c->z_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, tiles);
     c->t_block = g.t_block > 0 ? g.t_block : 2;
-    c->region_y = (c->kernel == THIIM_KERNEL_BLOCKED && g.tile_y != 0) ? g.tile_y : 8;
-    const int ox = 64 - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
+    const bool btile = c->kernel == THIIM_KERNEL_BLOCKED && g.tile_x != 0;
+    const bool compact = g.storage == THIIM_STORAGE_COMPACT;
+    c->region_x = btile ? g.tile_x : (compact ? 32 : 64);
+    c->region_y = btile ? g.tile_y : (compact ? 16 : 8);
+    const int ox = c->region_x - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
     const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
     c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles);
     return THIIM_OK;
@@ -153,7 +172,7 @@ int resolve_tiles(thiim_ctx* c) {
 
 // One THIIM iteration from buffer `src` into buffer `dst` (src != dst).
 hipError_t one_pass(thiim_ctx* c, int src, int dst) {
-    return thiim::launch_fused(c->coef, c->F[src], c->F[dst], c->geo, c->tile_x, c->tile_y,
+    return thiim::launch_fused(c->cv, c->F[src], c->F[dst], c->geo, c->tile_x, c->tile_y,
                                c->z_chunk, c->stream);
 }
 
@@ -242,25 +261,43 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
                            hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "profile copy"));
 
-    thiim::CoefArgs a;
-    a.eps = (const double2*)m->eps;
+    const bool compact = g->storage == THIIM_STORAGE_COMPACT;
+    thiim::CoefConst K;
+    K.tau = g->tau;
+    K.h = g->h;
+    K.omega = omega;
+    const double wt = omega * g->tau;
+    K.ph = make_double2(std::cos(wt), std::sin(wt));
+    K.phc = make_double2(std::cos(wt), -std::sin(wt));
+    K.ph2 = make_double2(std::cos(wt / 2), std::sin(wt / 2));
+    K.ph2c = make_double2(std::cos(wt / 2), -std::sin(wt / 2));
+    thiim::PlaneCoef* P = (thiim::PlaneCoef*)(c->ws + L.off_plane);
+    double2* cbase = (double2*)(c->ws + L.off_coef);
+    c->cv.compact = compact ? 1 : 0;
+    c->cv.C = compact ? nullptr : cbase;
+    c->cv.eps = compact ? cbase : nullptr;
+    c->cv.src = compact ? cbase + L.S : cbase + 24 * L.S;
+    c->cv.P = P;
+    c->cv.S = L.S;
+    c->cv.K = K;
+    c->coef = cbase;
+
+    thiim::BuildArgs a;
+    a.eps_in = (const double2*)m->eps;
     a.sig_e = c->sig_dev;
     a.sig_h = c->sig_dev + g->nz;
-    for (int s = 0; s < 4; ++s) a.src[s] = (const double2*)m->src[s];
-    a.coef = c->coef;
+    for (int s = 0; s < 4; ++s) a.src_in[s] = (const double2*)m->src[s];
+    a.C = compact ? nullptr : cbase;
+    a.eps_out = compact ? cbase : nullptr;
+    a.src_out = (double2*)c->cv.src;
+    a.P = P;
     a.S = L.S;
     a.N = L.N;
     a.nxy = (long long)g->nx * g->ny;
-    a.tau = g->tau;
-    a.h = g->h;
-    a.omega = omega;
-    const double wt = omega * g->tau;
-    a.ph = make_double2(std::cos(wt), std::sin(wt));
-    a.phc = make_double2(std::cos(wt), -std::sin(wt));
-    a.ph2 = make_double2(std::cos(wt / 2), std::sin(wt / 2));
-    a.ph2c = make_double2(std::cos(wt / 2), -std::sin(wt / 2));
+    a.nz = g->nz;
+    a.K = K;
     a.flag = c->flag;
-    e = thiim::launch_coeffs(a, c->stream);
+    e = thiim::launch_build(a, compact, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "coefficient launch"));
     e = thiim::launch_fill_zero(c->F[0], 24 * L.S, c->stream);  // both buffers
     if (e != hipSuccess) return bail(hip_fail(e, "zero fields"));
@@ -288,11 +325,12 @@ int thiim_iterate(thiim_ctx* c, int n) {
     for (int it = 0; it < n; ++it) {
         hipError_t e;
         if (c->kernel == THIIM_KERNEL_NAIVE) {
-            e = thiim::launch_naive(c->coef, c->F[c->cur], c->geo, c->z_chunk, c->stream);
+            e = thiim::launch_naive(c->cv, c->F[c->cur], c->geo, c->z_chunk, c->stream);
         } else if (c->kernel == THIIM_KERNEL_BLOCKED && c->t_block > 1 &&
                    n - it >= c->t_block) {
-            e = thiim::launch_blocked(c->coef, c->F[c->cur], c->F[1 - c->cur], c->geo,
-                                      c->t_block, c->region_y, c->bz_chunk, c->stream);
+            e = thiim::launch_blocked(c->cv, c->F[c->cur], c->F[1 - c->cur], c->geo,
+                                      c->t_block, c->region_x, c->region_y, c->bz_chunk,
+                                      c->stream);
             c->cur = 1 - c->cur;
             it += c->t_block - 1;
             c->iters += c->t_block - 1;
@@ -366,12 +404,18 @@ int thiim_set_fields(thiim_ctx* c, const double* src) {
 
 int thiim_get_coeffs(thiim_ctx* c, double* dst) {
     if (!c || !dst) return fail(THIIM_EINVAL, "ctx / dst is NULL");
-    for (int q = 0; q < 28; ++q) {
-        hipError_t e = hipMemcpyAsync(dst + 2 * q * c->L.N, c->coef + q * c->L.S, 16 * c->L.N,
-                                      hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) return hip_fail(e, "get_coeffs");
+    hipError_t e = hipSuccess;
+    if (c->cv.compact) {
+        e = thiim::launch_expand(c->cv, c->geo, (double2*)dst, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "get_coeffs expand");
+    } else {
+        for (int q = 0; q < 28; ++q) {
+            e = hipMemcpyAsync(dst + 2 * q * c->L.N, c->coef + q * c->L.S, 16 * c->L.N,
+                               hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "get_coeffs");
+        }
     }
-    hipError_t e = hipStreamSynchronize(c->stream);
+    e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? THIIM_OK : hip_fail(e, "get_coeffs sync");
 }
 

@@ -10,25 +10,60 @@ struct Geo {
     long long S;   // stride between arrays (double2 elements)
 };
 
-struct CoefArgs {
-    const double2* eps;      // (eps', eps'') per cell
-    const double* sig_e;     // nz, device
-    const double* sig_h;     // nz, device
-    const double2* src[4];   // S_Hx, S_Hy, S_Ex, S_Ey or null
-    double2* coef;           // 28 arrays, stride S
-    long long S, N, nxy;
+// Constants of the coefficient formulas (Eq. 3-5).
+struct CoefConst {
     double tau, h, omega;
     double2 ph, phc, ph2, ph2c;  // e^{iwt}, e^{-iwt}, e^{iwt/2}, e^{-iwt/2}
+};
+
+// Per-plane coefficient data (96 bytes).  H coefficients depend only on the
+// plane: sigma* = 0 on the x/y-difference parts, sigma_h(z) on H_xy, H_yx.
+struct PlaneCoef {
+    double2 th0, thz;  // t of H parts without / with the PML term
+    double2 ch0, chz;  // c of H parts without / with the PML term
+    double2 shz;       // Src scale of H_xy, H_yx (tau / d_H)
+    double sig_e;      // electric PML conductivity of E_xy, E_yx
+    int has_src;       // a source value on this plane is non-zero
+    int pad;
+};
+
+// Where the sweeps find their coefficients.
+//   full:    the 28 arrays of the paper's layout (t_q, c_q, 4 Src) at C
+//   compact: per-cell eps (1 array) + the 4 Src arrays; t, c derived on the
+//            fly by the same device functions that build the full arrays
+struct CoefView {
+    int compact;
+    const double2* C;    // full: 28 arrays
+    const double2* eps;  // compact: (eps', eps'') per cell
+    const double2* src;  // 4 Src arrays (full: C + 24*S)
+    const PlaneCoef* P;  // nz entries
+    long long S;
+    CoefConst K;
+};
+
+struct BuildArgs {
+    const double2* eps_in;   // (eps', eps'') per cell
+    const double* sig_e;     // nz, device
+    const double* sig_h;     // nz, device
+    const double2* src_in[4];  // S_Hx, S_Hy, S_Ex, S_Ey or null
+    double2* C;              // full: 28 arrays (else null)
+    double2* eps_out;        // compact: copy of eps (else null)
+    double2* src_out;        // 4 Src arrays
+    PlaneCoef* P;            // nz entries
+    long long S, N, nxy;
+    int nz;
+    CoefConst K;
     int* flag;               // set to 1 on invalid material data
 };
 
-hipError_t launch_coeffs(const CoefArgs& a, hipStream_t s);
-hipError_t launch_naive(const double2* C, double2* F, const Geo& g, int kchunk,
+hipError_t launch_build(const BuildArgs& a, bool compact, hipStream_t s);
+hipError_t launch_expand(const CoefView& cv, const Geo& g, double2* dst, hipStream_t s);
+hipError_t launch_naive(const CoefView& cv, double2* F, const Geo& g, int kchunk,
                         hipStream_t s);
-hipError_t launch_fused(const double2* C, const double2* A, double2* B, const Geo& g,
+hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                         int tile_x, int tile_y, int kchunk, hipStream_t s);
-hipError_t launch_blocked(const double2* C, const double2* A, double2* B, const Geo& g,
-                          int T, int ry, int kchunk, hipStream_t s);
+hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
+                          int T, int rx, int ry, int kchunk, hipStream_t s);
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
                         double* part, int nblk, double* out, hipStream_t s);
 hipError_t launch_fill_zero(double2* p, long long n, hipStream_t s);

@@ -1,18 +1,24 @@
 // HIP kernels of the THIIM solver for gfx950 (MI355X).
 //
-// Data layout in HBM: one workspace holding 28 coefficient arrays and two
-// 12-array field buffers (A, B), each array [nz][ny][nx] of double2
-// (interleaved re/im, x fastest -- the layout of Listings 1 and 2), with a
+// Data layout in HBM: one workspace holding the coefficient data and two
+// 12-array field buffers (A, B).  Every array is [nz][ny][nx] of double2
+// (interleaved re/im, x fastest -- the layout of Listings 1 and 2) with a
 // common stride S (elements, a multiple of 16 so every array starts on a
-// 256-byte boundary).  Lanes run along x, so every array access of a
+// 256-byte boundary).  Lanes run along x, so each array access of a
 // wavefront is 64 consecutive 16-byte values (1 KiB, fully coalesced).
 //
+// Coefficient storage (CoefView): either the paper's 28 arrays, or a compact
+// form -- per-cell eps plus per-plane tables -- from which every sweep derives
+// t and c with the same device functions that fill the 28 arrays, so both
+// storages give bit-identical iterates.
+//
 // Kernels
-//   k_coeffs      a0: the 28 coefficient arrays from eps and the PML profiles
-//   k_naive_h     a1: H half-step, in place, one HBM sweep (2.5D z streaming)
-//   k_naive_e     a2: E half-step, in place, one HBM sweep
-//   k_fused       a1+a2 in one HBM pass, A -> B, LDS-staged x-y tile
-//   k_resid_*     a5: FP64 residual / norm reduction (deterministic order)
+//   k_plane_table, k_build   a0: coefficient data from eps and the profiles
+//   k_expand                 the 28 arrays from compact storage (inspection)
+//   k_naive_h / k_naive_e    a1 / a2: one in-place HBM sweep per half-step
+//   k_fused                  a1 + a2 in one HBM pass, A -> B
+//   k_blocked                T iterations in one HBM pass, A -> B
+//   k_resid_*                a5: FP64 residual / norm reduction
 #include "thiim_device.h"
 #include "thiim_kernels.h"
 
@@ -74,80 +80,6 @@ __device__ __forceinline__ double2 cscale(double s, double2 a) {
 }
 
 // ---------------------------------------------------------------------------
-// a0: coefficients.  Eq. (4) with mu = 1:
-//   d_H = e^{iwt/2} + tau sigma*,  t = e^{-iwt/2}/d_H,  c = (tau/h)/d_H,
-//   Src = tau S_H / d_H.
-// Eq. (3) (eps' > 0):  d = 1 + tau sigma/eps',  t = e^{-iwt}/d,
-//   c = tau/(eps' h) e^{-iwt/2}/d,  Src = tau e^{-iwt} S_E / d.
-// Eq. (5) (eps' < 0):  d = 1 - tau sigma/eps',  t = e^{iwt}/d,
-//   c = -tau/(eps' h) e^{iwt/2}/d,  Src = -tau S_E / d.
-// sigma = w eps'' (+ sigma_e(z) on E_xy, E_yx); sigma* = sigma_h(z) on
-// H_xy, H_yx and 0 on the other H parts.
-// ---------------------------------------------------------------------------
-__global__ void k_coeffs(CoefArgs a) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.N;
-         p += stride) {
-        const int k = (int)(p / a.nxy);
-        const double2 e = a.eps[p];
-        if (!(e.x != 0.0) || !isfinite(e.x) || !isfinite(e.y)) {
-            a.flag[0] = 1;
-            continue;
-        }
-        double2* C = a.coef;
-        const long long S = a.S;
-        // H parts
-        const double2 dh0 = a.ph2;  // sigma* = 0
-        const double2 dhz = make_double2(a.ph2.x + a.tau * a.sig_h[k], a.ph2.y);
-        const double2 th0 = cdiv(a.ph2c, dh0), thz = cdiv(a.ph2c, dhz);
-        const double2 ch0 = cdiv(make_double2(a.tau / a.h, 0.0), dh0);
-        const double2 chz = cdiv(make_double2(a.tau / a.h, 0.0), dhz);
-        for (int q = 0; q < 6; ++q) {
-            const bool zax = (q == HXY || q == HYX);
-            C[q * S + p] = zax ? thz : th0;
-            C[(12 + q) * S + p] = zax ? chz : ch0;
-        }
-        const double2 sh = cdiv(make_double2(a.tau, 0.0), dhz);
-        {
-            const double2 s0 = a.src[0] ? a.src[0][p] : czero();
-            const double2 s1 = a.src[1] ? a.src[1][p] : czero();
-            C[SRC_HXY * S + p] = cmul(sh, s0);
-            C[SRC_HYX * S + p] = cmul(sh, s1);
-        }
-        // E parts
-        const double eps = e.x;
-        const double sig_mat = a.omega * e.y;
-        const double cs = a.tau / (eps * a.h);
-        double2 te[2], ce[2], se[2];  // [0]: no PML term, [1]: with sigma_e(z)
-        for (int z = 0; z < 2; ++z) {
-            const double sg = sig_mat + (z ? a.sig_e[k] : 0.0);
-            if (eps > 0.0) {
-                const double d = 1.0 + a.tau * sg / eps;
-                te[z] = cscale(1.0 / d, a.phc);
-                ce[z] = cscale(cs / d, a.ph2c);
-                se[z] = cscale(a.tau / d, a.phc);
-            } else {
-                const double d = 1.0 - a.tau * sg / eps;
-                te[z] = cscale(1.0 / d, a.ph);
-                ce[z] = cscale(-cs / d, a.ph2);
-                se[z] = make_double2(-a.tau / d, 0.0);
-            }
-        }
-        for (int q = 6; q < 12; ++q) {
-            const int z = (q == EXY || q == EYX) ? 1 : 0;
-            C[q * S + p] = te[z];
-            C[(12 + q) * S + p] = ce[z];
-        }
-        {
-            const double2 s2 = a.src[2] ? a.src[2][p] : czero();
-            const double2 s3 = a.src[3] ? a.src[3][p] : czero();
-            C[SRC_EXY * S + p] = cmul(se[1], s2);
-            C[SRC_EYX * S + p] = cmul(se[1], s3);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Addressing: every access is (uniform base of array q at plane k) + (32-bit
 // in-plane byte offset of the thread's cell).  The base lives in scalar
 // registers and the offset in one vector register, so the loads use the
@@ -187,18 +119,225 @@ __device__ __forceinline__ double2 pair_sum(const double2* __restrict__ F, long 
                                             int q, long long po, uint32_t boff) {
     return cadd(ldo(F + q * S + po, boff), ldo(F + (q + 1) * S + po, boff));
 }
-// coefficients t, c of the six parts starting at q0 and the two Src values
-__device__ __forceinline__ void load_coef6(const double2* __restrict__ C, long long S,
-                                           long long po, uint32_t boff, int q0, int s0,
-                                           double2 t[6], double2 c[6], double2& sa,
-                                           double2& sb) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        t[q] = ldo(C + (q0 + q) * S + po, boff);
-        c[q] = ldo(C + (12 + q0 + q) * S + po, boff);
+// ---------------------------------------------------------------------------
+// a0: coefficients (Eq. 3-5 solved for the new value).
+//   H (Eq. 4, mu = 1):  d_H = e^{iwt/2} + tau sigma*,  t = e^{-iwt/2}/d_H,
+//                       c = (tau/h)/d_H,  Src = tau S_H / d_H
+//   E (Eq. 3, eps'>0):  d = 1 + tau sigma/eps',  t = e^{-iwt}/d,
+//                       c = tau/(eps' h) e^{-iwt/2}/d,  Src = tau e^{-iwt} S_E/d
+//   E (Eq. 5, eps'<0):  d = 1 - tau sigma/eps',  t = e^{iwt}/d,
+//                       c = -tau/(eps' h) e^{iwt/2}/d,  Src = -tau S_E / d
+// sigma = w eps'' (+ sigma_e(z) on E_xy, E_yx); sigma* = sigma_h(z) on
+// H_xy, H_yx and 0 on the other H parts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ PlaneCoef plane_coef(double sig_h, double sig_e, const CoefConst& K) {
+    const double2 dhz = make_double2(K.ph2.x + K.tau * sig_h, K.ph2.y);
+    const double2 th = make_double2(K.tau / K.h, 0.0);
+    PlaneCoef pc;
+    pc.th0 = cdiv(K.ph2c, K.ph2);
+    pc.thz = cdiv(K.ph2c, dhz);
+    pc.ch0 = cdiv(th, K.ph2);
+    pc.chz = cdiv(th, dhz);
+    pc.shz = cdiv(make_double2(K.tau, 0.0), dhz);
+    pc.sig_e = sig_e;
+    pc.has_src = 0;
+    pc.pad = 0;
+    return pc;
+}
+
+// E coefficients of one cell: index 0 = parts with an x/y difference,
+// 1 = parts with a z difference (PML term sig_e added); s1 = Src scale.
+struct ECoef {
+    double2 t0, t1, c0, c1, s1;
+};
+__device__ __forceinline__ ECoef cell_e(double2 eps, double sig_e, const CoefConst& K) {
+    const double inv = 1.0 / eps.x;
+    const double cs = K.tau * inv / K.h;  // tau / (eps' h)
+    const double sg0 = K.omega * eps.y;
+    const double sg1 = sg0 + sig_e;
+    ECoef r;
+    if (eps.x > 0.0) {
+        const double r0 = 1.0 / (1.0 + K.tau * sg0 * inv);
+        const double r1 = 1.0 / (1.0 + K.tau * sg1 * inv);
+        r.t0 = cscale(r0, K.phc);
+        r.t1 = cscale(r1, K.phc);
+        r.c0 = cscale(cs * r0, K.ph2c);
+        r.c1 = cscale(cs * r1, K.ph2c);
+        r.s1 = cscale(K.tau * r1, K.phc);
+    } else {
+        const double r0 = 1.0 / (1.0 - K.tau * sg0 * inv);
+        const double r1 = 1.0 / (1.0 - K.tau * sg1 * inv);
+        r.t0 = cscale(r0, K.ph);
+        r.t1 = cscale(r1, K.ph);
+        r.c0 = cscale(-cs * r0, K.ph2);
+        r.c1 = cscale(-cs * r1, K.ph2);
+        r.s1 = make_double2(-K.tau * r1, 0.0);
     }
-    sa = ldo(C + s0 * S + po, boff);
-    sb = ldo(C + (s0 + 1) * S + po, boff);
+    return r;
+}
+
+__device__ __forceinline__ bool valid_eps(double2 e) {
+    return e.x != 0.0 && isfinite(e.x) && isfinite(e.y);
+}
+
+__global__ void k_plane_table(const double* __restrict__ sig_e, const double* __restrict__ sig_h,
+                              int nz, CoefConst K, PlaneCoef* __restrict__ P) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nz) P[k] = plane_coef(sig_h[k], sig_e[k], K);
+}
+
+// Per cell: validates eps, writes the t/c arrays (full) or the eps copy
+// (compact), the four Src arrays, and marks planes that carry a source.
+template <bool COMPACT>
+__global__ void k_build(BuildArgs a) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < a.N;
+         p += stride) {
+        const int k = (int)(p / a.nxy);
+        const double2 e = a.eps_in[p];
+        if (!valid_eps(e)) {
+            a.flag[0] = 1;
+            continue;
+        }
+        const PlaneCoef pc = a.P[k];
+        const ECoef r = cell_e(e, pc.sig_e, a.K);
+        const long long S = a.S;
+        if (COMPACT) {
+            a.eps_out[p] = e;
+        } else {
+            double2* C = a.C;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const bool z = (q == 0 || q == 2);  // H_xy, H_yx / E_xy, E_yx
+                C[q * S + p] = z ? pc.thz : pc.th0;
+                C[(12 + q) * S + p] = z ? pc.chz : pc.ch0;
+                C[(6 + q) * S + p] = z ? r.t1 : r.t0;
+                C[(18 + q) * S + p] = z ? r.c1 : r.c0;
+            }
+        }
+        double2 sv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sv[q] = a.src_in[q] ? a.src_in[q][p] : czero();
+        a.src_out[0 * S + p] = cmul(pc.shz, sv[0]);
+        a.src_out[1 * S + p] = cmul(pc.shz, sv[1]);
+        a.src_out[2 * S + p] = cmul(r.s1, sv[2]);
+        a.src_out[3 * S + p] = cmul(r.s1, sv[3]);
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) any = any || sv[q].x != 0.0 || sv[q].y != 0.0;
+        if (any) a.P[k].has_src = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient providers: t[6], c[6] and the two Src values of the six H or E
+// parts at one cell.  Src arrays are read only on planes that carry a source
+// (elsewhere they are exactly zero).
+// ---------------------------------------------------------------------------
+struct FullCoefs {
+    const double2* __restrict__ C;
+    const PlaneCoef* __restrict__ P;
+    long long S;
+    __device__ __forceinline__ void h(int k, long long po, uint32_t bo, double2 t[6],
+                                      double2 c[6], double2& sa, double2& sb) const {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            t[q] = ldo(C + q * S + po, bo);
+            c[q] = ldo(C + (12 + q) * S + po, bo);
+        }
+        sa = czero();
+        sb = czero();
+        if (P[k].has_src) {
+            sa = ldo(C + SRC_HXY * S + po, bo);
+            sb = ldo(C + SRC_HYX * S + po, bo);
+        }
+    }
+    __device__ __forceinline__ void e(int k, long long po, uint32_t bo, double2 t[6],
+                                      double2 c[6], double2& sa, double2& sb) const {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            t[q] = ldo(C + (6 + q) * S + po, bo);
+            c[q] = ldo(C + (18 + q) * S + po, bo);
+        }
+        sa = czero();
+        sb = czero();
+        if (P[k].has_src) {
+            sa = ldo(C + SRC_EXY * S + po, bo);
+            sb = ldo(C + SRC_EYX * S + po, bo);
+        }
+    }
+};
+
+struct CompactCoefs {
+    const double2* __restrict__ eps;
+    const double2* __restrict__ src;
+    const PlaneCoef* __restrict__ P;
+    long long S;
+    CoefConst K;
+    __device__ __forceinline__ void h(int k, long long po, uint32_t bo, double2 t[6],
+                                      double2 c[6], double2& sa, double2& sb) const {
+        const PlaneCoef pc = P[k];
+        t[0] = pc.thz; c[0] = pc.chz;
+        t[1] = pc.th0; c[1] = pc.ch0;
+        t[2] = pc.thz; c[2] = pc.chz;
+        t[3] = pc.th0; c[3] = pc.ch0;
+        t[4] = pc.th0; c[4] = pc.ch0;
+        t[5] = pc.th0; c[5] = pc.ch0;
+        sa = czero();
+        sb = czero();
+        if (pc.has_src) {
+            sa = ldo(src + 0 * S + po, bo);
+            sb = ldo(src + 1 * S + po, bo);
+        }
+    }
+    __device__ __forceinline__ void e(int k, long long po, uint32_t bo, double2 t[6],
+                                      double2 c[6], double2& sa, double2& sb) const {
+        const double sig_e = P[k].sig_e;
+        const int has_src = P[k].has_src;
+        const ECoef r = cell_e(ldo(eps + po, bo), sig_e, K);
+        t[0] = r.t1; c[0] = r.c1;
+        t[1] = r.t0; c[1] = r.c0;
+        t[2] = r.t1; c[2] = r.c1;
+        t[3] = r.t0; c[3] = r.c0;
+        t[4] = r.t0; c[4] = r.c0;
+        t[5] = r.t0; c[5] = r.c0;
+        sa = czero();
+        sb = czero();
+        if (has_src) {
+            sa = ldo(src + 2 * S + po, bo);
+            sb = ldo(src + 3 * S + po, bo);
+        }
+    }
+};
+
+// The 28 arrays of the full layout from compact storage, into a buffer with
+// array stride N (thiim_get_coeffs).
+__global__ void k_expand(CompactCoefs cp, Geo g, double2* __restrict__ dst) {
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const long long nxy = (long long)g.nx * g.ny;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+        const int k = (int)(p / nxy);
+        const long long po = k * nxy;
+        const uint32_t bo = 16u * (uint32_t)(p - po);
+        double2 t[6], c[6], sa, sb;
+        cp.h(k, po, bo, t, c, sa, sb);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            dst[q * N + p] = t[q];
+            dst[(12 + q) * N + p] = c[q];
+        }
+        dst[SRC_HXY * N + p] = ldo(cp.src + 0 * cp.S + po, bo);
+        dst[SRC_HYX * N + p] = ldo(cp.src + 1 * cp.S + po, bo);
+        cp.e(k, po, bo, t, c, sa, sb);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            dst[(6 + q) * N + p] = t[q];
+            dst[(18 + q) * N + p] = c[q];
+        }
+        dst[SRC_EXY * N + p] = ldo(cp.src + 2 * cp.S + po, bo);
+        dst[SRC_EYX * N + p] = ldo(cp.src + 3 * cp.S + po, bo);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -206,8 +345,8 @@ __device__ __forceinline__ void load_coef6(const double2* __restrict__ C, long l
 // keeping E_x, E_y of plane k-1 in registers (2.5D streaming).
 // Block 64 x 4, grid (nx/64, ny/4, z chunks).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_naive_h(const double2* __restrict__ C,
-                                                 double2* __restrict__ F, Geo g,
+template <class CP>
+__global__ __launch_bounds__(256) void k_naive_h(CP cp, double2* __restrict__ F, Geo g,
                                                  int kchunk) {
     const Tile T = tile_of((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kchunk - 1) / kchunk);
     const int i = T.bx * 64 + threadIdx.x;
@@ -246,7 +385,7 @@ __global__ __launch_bounds__(256) void k_naive_h(const double2* __restrict__ C,
         nb.ez_xm = has_xm ? pair_sum(E, S, 4, po, bxm) : czero();
         double2 h[6], t[6], c[6], sa, sb;
         load6(F, S, po, bo, h);
-        load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
+        cp.h(k, po, bo, t, c, sa, sb);
         update_h(h, t, c, sa, sb, nb);
         store6(F, S, po, bo, h);
         ex_zm = nb.ex;
@@ -258,8 +397,8 @@ __global__ __launch_bounds__(256) void k_naive_h(const double2* __restrict__ C,
 // a2 naive: E half-step in place.  Streams z downward keeping H_x, H_y of
 // plane k+1 in registers.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_naive_e(const double2* __restrict__ C,
-                                                 double2* __restrict__ F, Geo g,
+template <class CP>
+__global__ __launch_bounds__(256) void k_naive_e(CP cp, double2* __restrict__ F, Geo g,
                                                  int kchunk) {
     const Tile T = tile_of((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kchunk - 1) / kchunk);
     const int i = T.bx * 64 + threadIdx.x;
@@ -299,7 +438,7 @@ __global__ __launch_bounds__(256) void k_naive_e(const double2* __restrict__ C,
         nb.hz_xp = has_xp ? pair_sum(H, S, 4, po, bxp) : czero();
         double2 e[6], t[6], c[6], sa, sb;
         load6(E, S, po, bo, e);
-        load_coef6(C, S, po, bo, 6, SRC_EXY, t, c, sa, sb);
+        cp.e(k, po, bo, t, c, sa, sb);
         update_e(e, t, c, sa, sb, nb);
         store6(E, S, po, bo, e);
         hx_zp = nb.hx;
@@ -323,9 +462,8 @@ __global__ __launch_bounds__(256) void k_naive_e(const double2* __restrict__ C,
 // plane stay in registers.  A chunk [k0, k1) of planes recomputes H(k1) (not
 // stored) so that chunks are independent.
 // ---------------------------------------------------------------------------
-template <int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
-                                                  const double2* __restrict__ A,
+template <int TX, int TY, class CP>
+__global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restrict__ A,
                                                   double2* __restrict__ B, Geo g,
                                                   int kchunk) {
     constexpr int NT = TX * TY;
@@ -433,7 +571,7 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
                 nb.ez_xm = Es[2][eo - 1];
                 double2 h[6], t[6], c[6], sa, sb;
                 load6(A, S, po, bo, h);
-                load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
+                cp.h(k, po, bo, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
                 if (own_store && k < k1) store6(B, S, po, bo, h);
                 hx = cadd(h[0], h[1]);
@@ -453,7 +591,7 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
                 nb.ez_xm = Es[2][eh - 1];
                 double2 h[6], t[6], c[6], sa, sb;
                 load6(A, S, po, bh, h);
-                load_coef6(C, S, po, bh, 0, SRC_HXY, t, c, sa, sb);
+                cp.h(k, po, bh, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
                 hhx = cadd(h[0], h[1]);
                 hhy = cadd(h[2], h[3]);
@@ -474,7 +612,7 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
             nb.hz_xp = Hs[2][ho + 1];
             const long long pm = po - plane;
             double2 t[6], c[6], sa, sb;
-            load_coef6(C, S, pm, bo, 6, SRC_EXY, t, c, sa, sb);
+            cp.e(k - 1, pm, bo, t, c, sa, sb);
             update_e(eprev, t, c, sa, sb, nb);
             if (own_store) store6(BE, S, pm, bo, eprev);
         }
@@ -501,54 +639,54 @@ __global__ __launch_bounds__(TX* TY) void k_fused(const double2* __restrict__ C,
 // ---------------------------------------------------------------------------
 // Temporally blocked pass: T THIIM iterations per HBM pass, A -> B.
 //
-// A workgroup covers a region of 64 x RY columns (one wavefront per row,
-// lanes along x) and streams z.  Each thread keeps one column for the whole
+// A workgroup covers a region of RX x RY columns (lanes along x) and streams
+// z.  Each thread keeps one column for the whole
 // stream and for all T stages (fixed execution to data): the stage outputs it
 // needs one plane later -- old values and z-neighbour sums -- stay in its
 // registers, and the x/y-neighbour sums of every stage pass through LDS.
 // At step k stage s updates H_s at plane k-s+1 and E_s at plane k-s, so one
 // HBM read of plane k feeds all T stages (GPU form of the wavefront in z).
-// Only the centre (64-2T) x (RY-2T) columns are valid after T stages; they
+// Only the centre (RX-2T) x (RY-2T) columns are valid after T stages; they
 // are stored, the ring is recomputed by the neighbouring workgroups.  Region
 // cells beyond the ring read clamped neighbours: their (unused) results
 // never reach a stored cell.  z chunks overlap by T-1 planes.
-// Coefficients of the 40-array layout are re-read for every stage.
+// Each stage reads its own coefficients: with the 40-array layout that is
+// 448 B per column per stage, with the compact storage 16 B (eps).
 // ---------------------------------------------------------------------------
-template <int RY, int T>
-__global__ __launch_bounds__(64 * RY) void k_blocked(const double2* __restrict__ C,
-                                                     const double2* __restrict__ A,
+template <int RX, int RY, int T, class CP>
+__global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __restrict__ A,
                                                      double2* __restrict__ B, Geo g,
                                                      int kchunk) {
-    constexpr int R = 64 * RY;
-    constexpr int OX = 64 - 2 * T, OY = RY - 2 * T;  // stored tile
+    constexpr int R = RX * RY;
+    constexpr int OX = RX - 2 * T, OY = RY - 2 * T;  // stored tile
     static_assert(OY >= 1, "region too small for T stages");
     __shared__ double2 LE[T][3][R];     // E_{s} sums, s = 0..T-1 (current plane)
     __shared__ double2 LH[T][2][3][R];  // H_{s+1} sums, by step parity
 
     const long long S = g.S;
     const long long plane = (long long)g.nx * g.ny;
-    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+    const int lane = threadIdx.x % RX, row = threadIdx.x / RX;
     const Tile TT = tile_of((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
                             (g.nz + kchunk - 1) / kchunk);
     const int ux = TT.bx * OX - T + lane;  // unwrapped global column
     const int uy = TT.by * OY - T + row;
     int gi = ux, gj = uy;
     const bool valid = resolve_xy(g, gi, gj);
-    const bool own = lane >= T && lane < 64 - T && row >= T && row < RY - T &&
+    const bool own = lane >= T && lane < RX - T && row >= T && row < RY - T &&
                      ux < g.nx && uy < g.ny;
     const uint32_t bo = valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
-    const int me = row * 64 + lane;
-    const int xm = row * 64 + (lane > 0 ? lane - 1 : 0);
-    const int xp = row * 64 + (lane < 63 ? lane + 1 : 63);
-    const int ym = (row > 0 ? row - 1 : 0) * 64 + lane;
-    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * 64 + lane;
+    const int me = row * RX + lane;
+    const int xm = row * RX + (lane > 0 ? lane - 1 : 0);
+    const int xp = row * RX + (lane < RX - 1 ? lane + 1 : RX - 1);
+    const int ym = (row > 0 ? row - 1 : 0) * RX + lane;
+    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * RX + lane;
 
     const int k0 = TT.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
     const int ks = max(0, k0 - (T - 1));
     const int kend = min(k1 + T - 1, g.nz + T - 1);
 
-    for (int i = threadIdx.x; i < T * 3 * R; i += 64 * RY) {
+    for (int i = threadIdx.x; i < T * 3 * R; i += RX * RY) {
         (&LE[0][0][0])[i] = czero();
         (&LH[0][0][0][0])[i] = czero();
         (&LH[0][0][0][0])[i + T * 3 * R] = czero();
@@ -615,7 +753,7 @@ __global__ __launch_bounds__(64 * RY) void k_blocked(const double2* __restrict__
                 nb.ey_xm = LE[s - 1][1][xm];
                 nb.ez_xm = LE[s - 1][2][xm];
                 double2 t[6], c[6], sa, sb;
-                load_coef6(C, S, po, bo, 0, SRC_HXY, t, c, sa, sb);
+                cp.h(kh, po, bo, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
                 if (s == T && own && kh >= k0 && kh < k1) store6(B, S, po, bo, h);
             }
@@ -651,7 +789,7 @@ __global__ __launch_bounds__(64 * RY) void k_blocked(const double2* __restrict__
                 nb.hy_xp = LH[s - 1][par ^ 1][1][xp];
                 nb.hz_xp = LH[s - 1][par ^ 1][2][xp];
                 double2 t[6], c[6], sa, sb;
-                load_coef6(C, S, po, bo, 6, SRC_EXY, t, c, sa, sb);
+                cp.e(ke, po, bo, t, c, sa, sb);
                 update_e(e, t, c, sa, sb, nb);
                 if (s == T && own && ke >= k0 && ke < k1) store6(BE, S, po, bo, e);
             }
@@ -771,52 +909,89 @@ static int grid_1d(long long n, int block) {
     return (int)b;
 }
 
-hipError_t launch_coeffs(const CoefArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_coeffs, dim3(grid_1d(a.N, 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
 static int nchunks(const Geo& g, int kchunk) { return (g.nz + kchunk - 1) / kchunk; }
 
-hipError_t launch_naive(const double2* C, double2* F, const Geo& g, int kchunk,
-                        hipStream_t s) {
-    dim3 grid(((g.nx + 63) / 64) * ((g.ny + 3) / 4) * nchunks(g, kchunk));
-    hipLaunchKernelGGL(k_naive_h, grid, dim3(64, 4), 0, s, C, F, g, kchunk);
-    hipLaunchKernelGGL(k_naive_e, grid, dim3(64, 4), 0, s, C, F, g, kchunk);
+static FullCoefs full_of(const CoefView& v) { return FullCoefs{v.C, v.P, v.S}; }
+static CompactCoefs compact_of(const CoefView& v) {
+    return CompactCoefs{v.eps, v.src, v.P, v.S, v.K};
+}
+
+hipError_t launch_build(const BuildArgs& a, bool compact, hipStream_t s) {
+    hipLaunchKernelGGL(k_plane_table, dim3((a.nz + 255) / 256), dim3(256), 0, s, a.sig_e,
+                       a.sig_h, a.nz, a.K, a.P);
+    if (compact)
+        hipLaunchKernelGGL(k_build<true>, dim3(grid_1d(a.N, 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_build<false>, dim3(grid_1d(a.N, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_fused(const double2* C, const double2* A, double2* B, const Geo& g,
-                        int tile_x, int tile_y, int kchunk, hipStream_t s) {
+hipError_t launch_expand(const CoefView& cv, const Geo& g, double2* dst, hipStream_t s) {
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_expand, dim3(grid_1d(N, 256)), dim3(256), 0, s, compact_of(cv), g,
+                       dst);
+    return hipGetLastError();
+}
+
+template <class CP>
+static void naive_impl(const CP& cp, double2* F, const Geo& g, int kchunk, hipStream_t s) {
+    dim3 grid(((g.nx + 63) / 64) * ((g.ny + 3) / 4) * nchunks(g, kchunk));
+    hipLaunchKernelGGL(k_naive_h<CP>, grid, dim3(64, 4), 0, s, cp, F, g, kchunk);
+    hipLaunchKernelGGL(k_naive_e<CP>, grid, dim3(64, 4), 0, s, cp, F, g, kchunk);
+}
+
+hipError_t launch_naive(const CoefView& cv, double2* F, const Geo& g, int kchunk,
+                        hipStream_t s) {
+    if (cv.compact) naive_impl(compact_of(cv), F, g, kchunk, s);
+    else naive_impl(full_of(cv), F, g, kchunk, s);
+    return hipGetLastError();
+}
+
+template <class CP>
+static hipError_t fused_impl(const CP& cp, const double2* A, double2* B, const Geo& g,
+                             int tile_x, int tile_y, int kchunk, hipStream_t s) {
     dim3 grid(((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y) *
               nchunks(g, kchunk));
     if (tile_x == 64 && tile_y == 8)
-        hipLaunchKernelGGL((k_fused<64, 8>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_fused<64, 8, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk);
     else if (tile_x == 32 && tile_y == 8)
-        hipLaunchKernelGGL((k_fused<32, 8>), grid, dim3(256), 0, s, C, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_fused<32, 8, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk);
     else if (tile_x == 64 && tile_y == 4)
-        hipLaunchKernelGGL((k_fused<64, 4>), grid, dim3(256), 0, s, C, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_fused<64, 4, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk);
     else if (tile_x == 16 && tile_y == 16)
-        hipLaunchKernelGGL((k_fused<16, 16>), grid, dim3(256), 0, s, C, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_fused<16, 16, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_blocked(const double2* C, const double2* A, double2* B, const Geo& g,
-                          int T, int ry, int kchunk, hipStream_t s) {
-    const int ox = 64 - 2 * T, oy = ry - 2 * T;
-    if (oy < 1) return hipErrorInvalidValue;
+hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const Geo& g,
+                        int tile_x, int tile_y, int kchunk, hipStream_t s) {
+    return cv.compact ? fused_impl(compact_of(cv), A, B, g, tile_x, tile_y, kchunk, s)
+                      : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
+}
+
+template <class CP>
+static hipError_t blocked_impl(const CP& cp, const double2* A, double2* B, const Geo& g,
+                               int T, int rx, int ry, int kchunk, hipStream_t s) {
+    const int ox = rx - 2 * T, oy = ry - 2 * T;
+    if (ox < 1 || oy < 1) return hipErrorInvalidValue;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
-    if (T == 2 && ry == 8)
-        hipLaunchKernelGGL((k_blocked<8, 2>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
-    else if (T == 2 && ry == 6)
-        hipLaunchKernelGGL((k_blocked<6, 2>), grid, dim3(384), 0, s, C, A, B, g, kchunk);
-    else if (T == 1 && ry == 8)
-        hipLaunchKernelGGL((k_blocked<8, 1>), grid, dim3(512), 0, s, C, A, B, g, kchunk);
+    if (T == 2 && rx == 64 && ry == 8)
+        hipLaunchKernelGGL((k_blocked<64, 8, 2, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk);
+    else if (T == 2 && rx == 64 && ry == 6)
+        hipLaunchKernelGGL((k_blocked<64, 6, 2, CP>), grid, dim3(384), 0, s, cp, A, B, g, kchunk);
+    else if (T == 2 && rx == 32 && ry == 16)
+        hipLaunchKernelGGL((k_blocked<32, 16, 2, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
+                          int T, int rx, int ry, int kchunk, hipStream_t s) {
+    return cv.compact ? blocked_impl(compact_of(cv), A, B, g, T, rx, ry, kchunk, s)
+                      : blocked_impl(full_of(cv), A, B, g, T, rx, ry, kchunk, s);
 }
 
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,

@@ -1,0 +1,132 @@
+"""Summaries of rocprofv3 output for the THIIM sweeps.
+
+* ``kernel_stats_md``: the ``--kernel-trace --stats`` CSV as a markdown table
+  with achieved algorithmic bandwidth per kernel.
+* ``traffic_summary``: per-dispatch ``FETCH_SIZE`` / ``WRITE_SIZE`` (KiB) from
+  two ``--pmc`` runs, each scaled by what the same counter reads for a plain
+  device copy of known size run in the same process (the calibration copy of
+  ``bench.py --calib-copy``).  The result records a hash of the kernel
+  sources; ``bench.py`` reports the traffic only while that hash matches.
+
+Usage:
+    python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD
+    python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CALIB_BYTES = 2 ** 32  # the calibration copy reads and writes 4 GiB
+
+# algorithmic HBM bytes per cell and launch (complex128); see bench.py
+ALG_BYTES_PER_CELL = {
+    "k_naive_h<thiim::FullCoefs>": 480,
+    "k_naive_e<thiim::FullCoefs>": 480,
+    "k_naive_h<thiim::CompactCoefs>": 288,
+    "k_naive_e<thiim::CompactCoefs>": 304,
+    "k_fused<64, 8, thiim::FullCoefs>": 768,
+    "k_fused<64, 8, thiim::CompactCoefs>": 400,
+    "k_blocked<64, 8, 2, thiim::FullCoefs>": 768,
+    "k_blocked<32, 16, 2, thiim::CompactCoefs>": 400,
+    "k_blocked<64, 8, 2, thiim::CompactCoefs>": 400,
+}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(kernel_name: str) -> str:
+    n = kernel_name.split("(")[0].replace("void ", "").replace("thiim::", "", 1)
+    return n.strip()
+
+
+def _per_kernel(path):
+    agg = defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            agg[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]) * 1024.0)
+    return agg
+
+
+def _calibration(agg, expected):
+    for name, vals in agg.items():
+        if "copyBuffer" in name or "copy_kernel" in name or "elementwise_kernel" in name:
+            big = max(vals)
+            if big > 0.25 * expected:
+                return big / expected
+    raise RuntimeError("calibration copy not found in the counter file")
+
+
+def traffic_summary(fetch_csv, write_csv, n_cells, out_json, command):
+    fetch, write = _per_kernel(fetch_csv), _per_kernel(write_csv)
+    f_scale = _calibration(fetch, CALIB_BYTES)
+    w_scale = _calibration(write, CALIB_BYTES)
+    kernels = {}
+    for name in sorted(set(fetch) & set(write)):
+        if not name.startswith(("k_", "thiim::k_")):
+            continue
+        fb = sum(fetch[name]) / len(fetch[name]) / f_scale
+        wb = sum(write[name]) / len(write[name]) / w_scale
+        kernels[name] = {
+            "dispatches": len(fetch[name]),
+            "read_bytes_per_launch": fb,
+            "write_bytes_per_launch": wb,
+            "bytes_per_launch": fb + wb,
+            "bytes_per_cell": (fb + wb) / n_cells,
+            "alg_bytes_per_cell": ALG_BYTES_PER_CELL.get(name),
+        }
+    out = {"source_hash": source_hash(), "cells": n_cells,
+           "fetch_counter_scale": f_scale, "write_counter_scale": w_scale,
+           "command": command, "kernels": kernels}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def kernel_stats_md(stats_csv, n_cells, out_md, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# THIIM kernels: rocprofv3 kernel statistics", "",
+             "Command:", "", "```", command, "```", "",
+             f"Grid: {n_cells} cells.  Achieved = algorithmic bytes per launch / average "
+             "duration.", "",
+             "| kernel | calls | avg (ms) | min (ms) | max (ms) | alg. B/cell | achieved GB/s |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = short_name(r["Name"])
+        avg = float(r["AverageNs"]) / 1e6
+        b = ALG_BYTES_PER_CELL.get(name)
+        gbs = f"{b * n_cells / (avg * 1e-3) / 1e9:.0f}" if b else "-"
+        lines.append(f"| {name} | {r['Calls']} | {avg:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
+                     f"{float(r['MaxNs']) / 1e6:.3f} | {b if b else '-'} | {gbs} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main(argv):
+    if argv[0] == "traffic":
+        fetch, write, n, out, cmd = argv[1:6]
+        print(json.dumps(traffic_summary(fetch, write, int(n), out, cmd), indent=1))
+    elif argv[0] == "stats":
+        stats, n, out, cmd = argv[1:5]
+        kernel_stats_md(stats, int(n), out, cmd)
+        print(open(out).read())
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -33,11 +33,14 @@ def test_workspace_bytes_layout():
     g512 = thiim.make_grid((512, 512, 512))
     b512 = thiim.thiim_workspace_bytes(g512)
     assert abs(b512 - 52 * 16 * 512 ** 3) < 2 ** 20  # 111.7 GB
+    c512 = thiim.thiim_workspace_bytes(thiim.make_grid((512, 512, 512), storage="compact"))
+    assert abs(c512 - 29 * 16 * 512 ** 3) < 2 ** 20  # eps + 4 Src + 24 fields
 
 
 @pytest.mark.parametrize("field,value", [("nx", 1), ("nz", 0), ("tau", 0.6), ("tau", 0.0),
                                          ("h", -1.0), ("bc_x", 2), ("kernel", 9),
-                                         ("tile_x", 48), ("z_chunk", -1), ("t_block", 99)])
+                                         ("tile_x", 48), ("z_chunk", -1), ("t_block", 99),
+                                         ("storage", 2)])
 def test_invalid_grid_rejected(field, value):
     g = thiim.make_grid((10, 10, 10))
     setattr(g, field, value)

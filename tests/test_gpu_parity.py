@@ -48,10 +48,11 @@ def _with_back_cells(pb, seed):
     return pb
 
 
-def test_coefficients_match_oracle():
+@pytest.mark.parametrize("storage", ["full", "compact"])
+def test_coefficients_match_oracle(storage):
     _require_gpu()
     pb = _with_back_cells(inputs.random_problem(17, 13, 11, seed=3), 5)
-    s = thiim.Solver(pb, kernel="naive")
+    s = thiim.Solver(pb, kernel="naive", storage=storage)
     cg = s.coeffs().cpu().numpy()
     co = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
     for q in range(28):
@@ -59,14 +60,16 @@ def test_coefficients_match_oracle():
         assert np.all(err <= 2e-15 * np.abs(co[q]) + 1e-300), q
 
 
-@pytest.mark.parametrize("kernel", ["naive", "fused", "blocked"])
-def test_c1_layered_textured_200_iterations(kernel):
+@pytest.mark.parametrize("kernel,storage", [("naive", "full"), ("fused", "full"),
+                                            ("blocked", "full"), ("fused", "compact"),
+                                            ("blocked", "compact")])
+def test_c1_layered_textured_200_iterations(kernel, storage):
     """24 x 24 interior cells + 2 x 6 PML planes, three textured layers,
     normal-incidence x-polarised source, 200 iterations."""
     _require_gpu()
     pb = inputs.solar_cell(24, 24, 36, seed=1, npml=6)
     _, xo = _oracle_run(pb, 200)
-    _, xg = _gpu_run(pb, 200, kernel=kernel)
+    _, xg = _gpu_run(pb, 200, kernel=kernel, storage=storage)
     assert _rel(xg.cpu().numpy(), xo) < 1e-12
 
 
@@ -84,10 +87,18 @@ def test_random_ragged_problem(bcx, bcy):
             _, xf = _gpu_run(pb, 25, kernel="fused", tile=tile, z_chunk=zc)
             assert torch.equal(xf, xn), (tile, zc)
     # temporally blocked: 12 two-iteration passes + 1 fused remainder
-    for tile in [(64, 8), (64, 6)]:
-        for zc in (0, 3, 5, 64):
-            _, xb = _gpu_run(pb, 25, kernel="blocked", tile=tile, z_chunk=zc)
-            assert torch.equal(xb, xn), ("blocked", tile, zc)
+    for storage in ("full", "compact"):
+        for tile in [(64, 8), (64, 6), (32, 16)]:
+            for zc in (0, 3, 5, 64):
+                _, xb = _gpu_run(pb, 25, kernel="blocked", tile=tile, z_chunk=zc,
+                                 storage=storage)
+                assert torch.equal(xb, xn), ("blocked", storage, tile, zc)
+    # compact storage: the same iterates from derived coefficients
+    _, xnc = _gpu_run(pb, 25, kernel="naive", storage="compact")
+    assert torch.equal(xnc, xn)
+    for tile in [(64, 8), (32, 8), (64, 4), (16, 16)]:
+        _, xf = _gpu_run(pb, 25, kernel="fused", tile=tile, storage="compact")
+        assert torch.equal(xf, xn), ("fused compact", tile)
 
 
 def test_tiny_grids_wrap_many_times():
@@ -100,9 +111,11 @@ def test_tiny_grids_wrap_many_times():
         _, xn = _gpu_run(pb, 15, kernel="naive")
         _, xf = _gpu_run(pb, 15, kernel="fused")
         _, xb = _gpu_run(pb, 15, kernel="blocked")
+        _, xbc = _gpu_run(pb, 15, kernel="blocked", storage="compact")
         assert _rel(xn.cpu().numpy(), xo) < 1e-12
         assert torch.equal(xf, xn)
         assert torch.equal(xb, xn)
+        assert torch.equal(xbc, xn)
 
 
 def test_zero_source_stays_zero():
@@ -158,7 +171,7 @@ def test_full_size_flat_stack_512():
         pytest.skip("needs the 288 GB of an MI355X")
     n = 512
     pb = inputs.solar_cell(n, n, n, seed=3, npml=6, flat=True)
-    s = thiim.Solver(pb, kernel="blocked")
+    s = thiim.Solver(pb, kernel="blocked", storage="compact")
     s.iterate(100)
     x = s.fields()
     small = inputs.solar_cell(2, 2, n, seed=3, npml=6, flat=True)
