@@ -71,6 +71,15 @@ extern "C" {
                                  * derived in the sweeps from eps and per-plane
                                  * tables by the same formulas */
 
+/* Arithmetic of thiim_solve. */
+#define THIIM_PRECISION_FP64 0  /* every sweep in complex128 */
+#define THIIM_PRECISION_MIXED 1 /* defect correction: FP64 residual, correction
+                                 * accumulation and norms; the correction
+                                 * equation (I - M) d = r approximated by
+                                 * complex64 sweeps d <- M d + r (M: the linear
+                                 * part of one THIIM iteration).  Needs
+                                 * THIIM_STORAGE_COMPACT. */
+
 typedef struct thiim_ctx thiim_ctx;
 
 typedef struct {
@@ -80,12 +89,15 @@ typedef struct {
     double tau;       /* pseudo-time step, 0 < tau <= h / sqrt(3) */
     int kernel;       /* THIIM_KERNEL_* */
     int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED: 0 (auto,
-                       * = 2), 1 or 2; a remainder runs through the fused sweep */
+                       * = 2), 1 or 2; a remainder runs through the fused sweep.
+                       * With THIIM_PRECISION_MIXED, 3 is also allowed and then
+                       * applies to the complex64 inner sweeps only */
     int tile_x, tile_y; /* fused sweep: tile 64x8, 32x8, 64x4 or 16x16; blocked
                          * sweep: region 64x8, 64x6 or 32x16 (columns x rows) of
                          * which the centre (x-2T) x (y-2T) is stored; 0x0 = auto */
     int z_chunk;      /* z planes per workgroup stream (0 = auto) */
     int storage;      /* THIIM_STORAGE_FULL or THIIM_STORAGE_COMPACT */
+    int precision;    /* THIIM_PRECISION_FP64 or THIIM_PRECISION_MIXED */
     void *stream;     /* hipStream_t */
 } thiim_grid;
 
@@ -130,8 +142,11 @@ int thiim_iterate(thiim_ctx *ctx, int n);
  * Does not advance x.  Synchronising; THIIM_EDIVERGED if not finite. */
 int thiim_residual(thiim_ctx *ctx, double *rel_res);
 
-/* Iterates until thiim_residual <= tol (checked every check_every
- * iterations) or max_it iterations.  *iters, *rel_res may be NULL.
+/* Iterates until thiim_residual <= tol or max_it sweeps, from the current
+ * state.  FP64: the residual is checked every check_every iterations.
+ * MIXED: each defect-correction step is one FP64 sweep (the residual) plus
+ * check_every complex64 inner sweeps (rounded up to whole blocked passes).
+ * *iters (sweeps done, both precisions) and *rel_res may be NULL.
  * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
 int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
                 int *iters, double *rel_res);

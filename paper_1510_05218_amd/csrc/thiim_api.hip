@@ -38,6 +38,7 @@ struct Layout {
     size_t off_plane; // nz PlaneCoef
     size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
     size_t off_a, off_b;
+    size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
     size_t total;
 };
 
@@ -58,6 +59,13 @@ Layout layout_of(const thiim_grid* g) {
     off += (size_t)12 * L.S * 16;
     L.off_b = off;
     off += (size_t)12 * L.S * 16;
+    L.off_r32 = L.off_d32 = 0;
+    if (g->precision == THIIM_PRECISION_MIXED) {
+        L.off_r32 = off;
+        off += (size_t)12 * L.S * 8;
+        L.off_d32 = off;
+        off += (size_t)24 * L.S * 8;
+    }
     L.total = off;
     return L;
 }
@@ -76,7 +84,12 @@ int check_grid(const thiim_grid* g) {
         return fail(THIIM_EINVAL, "tau must satisfy 0 < tau <= h/sqrt(3) (CFL)");
     if (g->kernel < THIIM_KERNEL_AUTO || g->kernel > THIIM_KERNEL_BLOCKED)
         return fail(THIIM_EINVAL, "unknown kernel");
-    if (g->t_block < 0 || g->t_block > 2) return fail(THIIM_EINVAL, "t_block must be 0 (auto), 1 or 2");
+    if (g->precision != THIIM_PRECISION_FP64 && g->precision != THIIM_PRECISION_MIXED)
+        return fail(THIIM_EINVAL, "precision must be FP64 or MIXED");
+    if (g->precision == THIIM_PRECISION_MIXED && g->storage != THIIM_STORAGE_COMPACT)
+        return fail(THIIM_EINVAL, "mixed precision needs the compact coefficient storage");
+    if (g->t_block < 0 || g->t_block > (g->precision == THIIM_PRECISION_MIXED ? 3 : 2))
+        return fail(THIIM_EINVAL, "t_block must be 0 (auto), 1 or 2 (3 with mixed precision)");
     if (g->storage != THIIM_STORAGE_FULL && g->storage != THIIM_STORAGE_COMPACT)
         return fail(THIIM_EINVAL, "storage must be FULL or COMPACT");
     if ((long long)g->nx * g->ny * 16 > 0xFFFFFFFFLL)
@@ -122,6 +135,9 @@ struct thiim_ctx {
     int kernel;  // resolved THIIM_KERNEL_*
     int tile_x, tile_y, z_chunk;      // fused sweep
     int t_block, region_x, region_y, bz_chunk;  // blocked sweep
+    float2* r32;                                // mixed precision buffers
+    float2* d32[2];
+    int inner_t, inner_rx, inner_ry, inner_chunk;
 };
 
 namespace {
@@ -159,7 +175,7 @@ int resolve_tiles(thiim_ctx* c) {
     const long long tiles = (long long)((g.nx + c->tile_x - 1) / c->tile_x) *
                             ((g.ny + c->tile_y - 1) / c->tile_y);
     c->z_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, tiles);
-    c->t_block = g.t_block > 0 ? g.t_block : 2;
+    c->t_block = g.t_block > 0 ? (g.t_block > 2 ? 2 : g.t_block) : 2;
     const bool btile = c->kernel == THIIM_KERNEL_BLOCKED && g.tile_x != 0;
     const bool compact = g.storage == THIIM_STORAGE_COMPACT;
     c->region_x = btile ? g.tile_x : (compact ? 32 : 64);
@@ -167,6 +183,13 @@ int resolve_tiles(thiim_ctx* c) {
     const int ox = c->region_x - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
     const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
     c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles);
+    // complex64 inner sweeps of the mixed solver: region 32 x 16, T = 2 or 3
+    c->inner_t = g.t_block >= 2 ? g.t_block : 2;
+    c->inner_rx = 32;
+    c->inner_ry = 16;
+    const long long itiles = (long long)((g.nx + 32 - 2 * c->inner_t - 1) / (32 - 2 * c->inner_t)) *
+                             ((g.ny + 16 - 2 * c->inner_t - 1) / (16 - 2 * c->inner_t));
+    c->inner_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, itiles);
     return THIIM_OK;
 }
 
@@ -242,6 +265,9 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->coef = (double2*)(c->ws + L.off_coef);
     c->F[0] = (double2*)(c->ws + L.off_a);
     c->F[1] = (double2*)(c->ws + L.off_b);
+    c->r32 = L.off_r32 ? (float2*)(c->ws + L.off_r32) : nullptr;
+    c->d32[0] = L.off_d32 ? (float2*)(c->ws + L.off_d32) : nullptr;
+    c->d32[1] = L.off_d32 ? c->d32[0] + 12 * L.S : nullptr;
     c->cur = 0;
     c->iters = 0;
     c->geo = Geo{g->nx, g->ny, g->nz, g->bc_x, g->bc_y, L.S};
@@ -358,11 +384,102 @@ int thiim_residual(thiim_ctx* c, double* rel_res) {
     return THIIM_OK;
 }
 
+namespace {
+
+// Mixed-precision defect correction (see THIIM_PRECISION_MIXED).
+//
+// Each step: FP64 sweep Phi(x), r = Phi(x) - x (FP64 norms; complex64 copy
+// with the invisible split differences dropped), d = r then d <- M d + r in
+// complex64, x += d in FP64.  Rounding a correction to complex64 also puts
+// single-precision noise into the modes that one iteration only rotates by
+// l = e^{-iw tau} (curl-free H where sigma* = 0, curl-free E in lossless
+// cells): they never decay and hold the residual at ~1e-6.  When a step
+// gains less than kStall and kSpacing steps have passed, one FP64 step
+// x <- (Phi(x) - l x)/(1 - l) removes them (it keeps the fixed point); its
+// gain on other modes is |mu - l|/|1 - l|, hence the spacing; and if the
+// residual one correction after a deflation is above kHarm times its value
+// before it (weakly damped modes amplified, e.g. in lossless inclusions),
+// deflation stays off for the rest of the solve.
+constexpr double kStall = 0.9;
+constexpr int kSpacing = 6;
+constexpr double kHarm = 2.0;
+
+int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, double* rel_res) {
+    const int other = 1 - c->cur;
+    const int T = c->inner_t;
+    const int passes = (inner - 1 + T - 1) / T;  // inner sweeps after d = r
+    const double wt = c->omega * c->g.tau;
+    const double2 lam = make_double2(std::cos(wt), -std::sin(wt));
+    const double2 den = make_double2(1.0 - lam.x, -lam.y);  // 1 - l
+    const double dd = den.x * den.x + den.y * den.y;
+    const double2 a = make_double2(den.x / dd, -den.y / dd);  // 1/(1 - l)
+    const double2 b = make_double2(-(lam.x * a.x - lam.y * a.y), -(lam.x * a.y + lam.y * a.x));
+    int done = 0, since = kSpacing;
+    double r = INFINITY, prev = INFINITY, r_defl = -1.0;
+    bool defl_on = true;
+    for (;;) {
+        // FP64: Phi(x) into the other buffer, r = Phi(x) - x (complex64 copy)
+        hipError_t e = one_pass(c, c->cur, other);
+        if (e != hipSuccess) return hip_fail(e, "mixed: residual sweep");
+        e = thiim::launch_defect(c->F[c->cur], c->F[other], c->r32, c->cv.P, c->L.S, c->L.N,
+                                 (long long)c->g.nx * c->g.ny, c->part, kResidBlocks, c->out,
+                                 c->stream);
+        if (e != hipSuccess) return hip_fail(e, "mixed: defect");
+        double host[2];
+        e = hipMemcpyAsync(host, c->out, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "mixed: residual sync");
+        done += 1;
+        r = std::sqrt(host[0]) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
+        if (!std::isfinite(r)) {
+            if (iters) *iters = done;
+            if (rel_res) *rel_res = r;
+            return fail(THIIM_EDIVERGED, "residual is not finite");
+        }
+        if (r <= tol || done >= max_it) break;
+        if (r_defl > 0.0 && since == 1) {
+            if (r > kHarm * r_defl) defl_on = false;
+            r_defl = -1.0;
+        }
+        if (defl_on && r > kStall * prev && since >= kSpacing) {
+            e = thiim::launch_deflate(c->F[c->cur], c->F[other], a, b, c->L.S, c->L.N, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "mixed: deflate");
+            since = 0;
+            prev = r;
+            r_defl = r;
+            continue;
+        }
+        // complex64: d = r, then d <- M d + r
+        e = thiim::launch_copy32(c->r32, c->d32[0], c->L.S, c->L.N, c->stream);
+        int di = 0;
+        for (int p = 0; e == hipSuccess && p < passes; ++p) {
+            e = thiim::launch_inner32(c->cv, c->r32, c->d32[di], c->d32[1 - di], c->geo, T,
+                                      c->inner_rx, c->inner_ry, c->inner_chunk, c->stream);
+            di = 1 - di;
+        }
+        if (e == hipSuccess) e = thiim::launch_accum(c->F[c->cur], c->d32[di], c->L.S, c->L.N,
+                                                     c->stream);
+        if (e != hipSuccess) return hip_fail(e, "mixed: inner sweeps");
+        done += passes * T;           // sweeps run (d = r is a copy)
+        c->iters += 1 + passes * T;   // equivalent plain iterations
+        since += 1;
+        prev = r;
+    }
+    if (iters) *iters = done;
+    if (rel_res) *rel_res = r;
+    if (r > tol) return fail(THIIM_ENOTCONV, "iteration limit reached before tolerance");
+    return THIIM_OK;
+}
+
+}  // namespace
+
 int thiim_solve(thiim_ctx* c, double tol, int max_it, int check_every, int* iters,
                 double* rel_res) {
     if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
     if (!(tol > 0.0) || max_it < 0 || check_every < 1)
         return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1");
+    if (c->g.precision == THIIM_PRECISION_MIXED)
+        return solve_mixed(c, tol, max_it, check_every, iters, rel_res);
     int done = 0;
     double r = INFINITY;
     int rc = thiim_residual(c, &r);

@@ -64,6 +64,16 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                         int tile_x, int tile_y, int kchunk, hipStream_t s);
 hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                           int T, int rx, int ry, int kchunk, hipStream_t s);
+hipError_t launch_inner32(const CoefView& cv, const float2* r, const float2* A, float2* B,
+                          const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s);
+hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
+                         long long S, long long N, long long nxy, double* part, int nblk,
+                         double* out, hipStream_t s);
+hipError_t launch_accum(double2* X, const float2* D, long long S, long long N, hipStream_t s);
+hipError_t launch_deflate(double2* X, const double2* Y, double2 a, double2 b, long long S,
+                          long long N, hipStream_t s);
+hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
+                         hipStream_t s);
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
                         double* part, int nblk, double* out, hipStream_t s);
 hipError_t launch_fill_zero(double2* p, long long n, hipStream_t s);

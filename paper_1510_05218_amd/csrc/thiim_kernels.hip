@@ -119,6 +119,34 @@ __device__ __forceinline__ double2 pair_sum(const double2* __restrict__ F, long 
                                             int q, long long po, uint32_t boff) {
     return cadd(ldo(F + q * S + po, boff), ldo(F + (q + 1) * S + po, boff));
 }
+// complex64 arrays share the cell indexing; their byte offset is half the
+// complex128 one.
+__device__ __forceinline__ float2 ldo(const float2* __restrict__ b, uint32_t boff16) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(b), (short)0, -1, 0x00020000);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, boff16 >> 1, 0, 0);
+    return __builtin_bit_cast(float2, v);
+}
+__device__ __forceinline__ void sto(float2* __restrict__ b, uint32_t boff16, float2 v) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(b, (short)0, -1, 0x00020000);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff16 >> 1, 0, 0);
+}
+template <class V>
+__device__ __forceinline__ void load6v(const V* __restrict__ F, long long S, long long po,
+                                       uint32_t bo, V v[6]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = ldo(F + q * S + po, bo);
+}
+template <class V>
+__device__ __forceinline__ void store6v(V* __restrict__ F, long long S, long long po,
+                                        uint32_t bo, const V v[6]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sto(F + q * S + po, bo, v[q]);
+}
+
 // ---------------------------------------------------------------------------
 // a0: coefficients (Eq. 3-5 solved for the new value).
 //   H (Eq. 4, mu = 1):  d_H = e^{iwt/2} + tau sigma*,  t = e^{-iwt/2}/d_H,
@@ -307,6 +335,89 @@ struct CompactCoefs {
             sa = ldo(src + 2 * S + po, bo);
             sb = ldo(src + 3 * S + po, bo);
         }
+    }
+};
+
+// Sweep policies: the complex type of the fields, the source mask, and the
+// coefficients / sources of the six H or E parts of one cell.
+//   Pol64<CP>: complex128 THIIM sweep with the paper's sources (Src of the
+//              z-difference parts), coefficients from CP.
+//   Pol32:     complex64 sweep d <- M d + r of the mixed-precision solver: the
+//              same coefficients (derived in FP64, rounded) and the residual r
+//              as the source of all twelve parts.
+template <class CP>
+struct Pol64 {
+    using V = double2;
+    static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
+    static constexpr bool H_SRC_AFTER = false;
+    static constexpr bool CARRY = false;
+    CP cp;
+    __device__ __forceinline__ void hcoef(int k, long long po, uint32_t bo, V t[6], V c[6],
+                                          V src[6]) const {
+        double2 sa, sb;
+        cp.h(k, po, bo, t, c, sa, sb);
+        src[0] = sa;
+        src[2] = sb;
+        src[1] = src[3] = src[4] = src[5] = czero();
+    }
+    __device__ __forceinline__ void ecoef(int k, long long po, uint32_t bo, V t[6], V c[6],
+                                          V src[6]) const {
+        double2 sa, sb;
+        cp.e(k, po, bo, t, c, sa, sb);
+        src[0] = sa;
+        src[2] = sb;
+        src[1] = src[3] = src[4] = src[5] = czero();
+    }
+};
+
+__device__ __forceinline__ float2 to32(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
+
+// In the correction equation the E half-step must see M_H d, the H update
+// without its source: the source r_H is added to the H parts only after their
+// sums have been formed (H_SRC_AFTER).  Then one sweep is exactly
+// d <- M d + r (with the source inside the H update it would be
+// M d + (r_H, r_E + c_E D+ r_H)).
+struct Pol32 {
+    using V = float2;
+    static constexpr int HMASK = 0, EMASK = SRC_MASK_ALL;
+    static constexpr bool H_SRC_AFTER = true;
+    // sources and eps are loaded once, by the first stage, and handed down
+    // the stage pipeline in registers (each later stage works one plane lower)
+    static constexpr bool CARRY = true;
+    CompactCoefs cp;
+    const float2* __restrict__ r;  // 12 arrays, stride S
+    __device__ __forceinline__ void load_h_src(long long po, uint32_t bo, V src[6]) const {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) src[q] = ldo(r + q * cp.S + po, bo);
+    }
+    __device__ __forceinline__ void load_e_src(long long po, uint32_t bo, V src[6]) const {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) src[q] = ldo(r + (6 + q) * cp.S + po, bo);
+    }
+    __device__ __forceinline__ double2 load_eps(long long po, uint32_t bo) const {
+        return ldo(cp.eps + po, bo);
+    }
+    __device__ __forceinline__ void hcoef_c(int k, V t[6], V c[6]) const {
+        const PlaneCoef pc = cp.P[k];
+        const float2 tz = to32(pc.thz), t0 = to32(pc.th0), cz = to32(pc.chz), c0 = to32(pc.ch0);
+        t[0] = tz; c[0] = cz;
+        t[1] = t0; c[1] = c0;
+        t[2] = tz; c[2] = cz;
+        t[3] = t0; c[3] = c0;
+        t[4] = t0; c[4] = c0;
+        t[5] = t0; c[5] = c0;
+    }
+    __device__ __forceinline__ void ecoef_c(int k, double2 eps, V t[6], V c[6]) const {
+        const ECoef e = cell_e(eps, cp.P[k].sig_e, cp.K);
+        const float2 t1 = to32(e.t1), t0 = to32(e.t0), c1 = to32(e.c1), c0 = to32(e.c0);
+        t[0] = t1; c[0] = c1;
+        t[1] = t0; c[1] = c0;
+        t[2] = t1; c[2] = c1;
+        t[3] = t0; c[3] = c0;
+        t[4] = t0; c[4] = c0;
+        t[5] = t0; c[5] = c0;
     }
 };
 
@@ -653,15 +764,16 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
 // Each stage reads its own coefficients: with the 40-array layout that is
 // 448 B per column per stage, with the compact storage 16 B (eps).
 // ---------------------------------------------------------------------------
-template <int RX, int RY, int T, class CP>
-__global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __restrict__ A,
-                                                     double2* __restrict__ B, Geo g,
-                                                     int kchunk) {
+template <int RX, int RY, int T, class P>
+__global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* __restrict__ A,
+                                                    typename P::V* __restrict__ B, Geo g,
+                                                    int kchunk) {
+    using V = typename P::V;
     constexpr int R = RX * RY;
     constexpr int OX = RX - 2 * T, OY = RY - 2 * T;  // stored tile
     static_assert(OY >= 1, "region too small for T stages");
-    __shared__ double2 LE[T][3][R];     // E_{s} sums, s = 0..T-1 (current plane)
-    __shared__ double2 LH[T][2][3][R];  // H_{s+1} sums, by step parity
+    __shared__ V LE[T][3][R];     // E_{s} sums, s = 0..T-1 (current plane)
+    __shared__ V LH[T][2][3][R];  // H_{s+1} sums, by step parity
 
     const long long S = g.S;
     const long long plane = (long long)g.nx * g.ny;
@@ -687,62 +799,84 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __rest
     const int kend = min(k1 + T - 1, g.nz + T - 1);
 
     for (int i = threadIdx.x; i < T * 3 * R; i += RX * RY) {
-        (&LE[0][0][0])[i] = czero();
-        (&LH[0][0][0][0])[i] = czero();
-        (&LH[0][0][0][0])[i + T * 3 * R] = czero();
+        (&LE[0][0][0])[i] = vzero<V>();
+        (&LH[0][0][0][0])[i] = vzero<V>();
+        (&LH[0][0][0][0])[i + T * 3 * R] = vzero<V>();
     }
 
-    const double2* AE = A + 6 * S;
-    double2* BE = B + 6 * S;
+    const V* AE = A + 6 * S;
+    V* BE = B + 6 * S;
 
     // carried state
-    double2 e0p[6];            // E_0 parts at plane k-1
-    double2 hc[T][6];          // H_s parts at plane k-s (s = 1..T-1 used)
-    double2 ep[T][6];          // E_s parts at plane k-1-s (s = 1..T-1 used)
-    double2 hTx = czero(), hTy = czero(), hTz = czero();  // H_T sums, plane k-T
+    V e0p[6];    // E_0 parts at plane k-1
+    V hc[T][6];  // H_s parts at plane k-s (s = 1..T-1 used)
+    V hcs[T][3]; // their sums without the source (H_SRC_AFTER policies)
+    V ep[T][6];  // E_s parts at plane k-1-s (s = 1..T-1 used)
+    V hTx = vzero<V>(), hTy = vzero<V>(), hTz = vzero<V>();  // H_T sums, plane k-T
+    // CARRY policies: sources of stage s at slot s-1 (H: plane k-s+1, E: plane
+    // k-s) and eps of the E plane of stage s
+    V rHq[T][6], rEq[T][6];
+    double2 epsq[T];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        e0p[q] = czero();
+    for (int s = 0; s < T; ++s) {
+        epsq[s] = make_double2(1.0, 0.0);
 #pragma unroll
-        for (int s = 0; s < T; ++s) {
-            hc[s][q] = czero();
-            ep[s][q] = czero();
+        for (int q = 0; q < 6; ++q) {
+            rHq[s][q] = vzero<V>();
+            rEq[s][q] = vzero<V>();
         }
     }
-    if (ks > 0 && valid) load6(AE, S, (ks - 1) * plane, bo, e0p);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        e0p[q] = vzero<V>();
+#pragma unroll
+        for (int s = 0; s < T; ++s) {
+            hc[s][q] = vzero<V>();
+            ep[s][q] = vzero<V>();
+            if (q < 3) hcs[s][q] = vzero<V>();
+        }
+    }
+    if (ks > 0 && valid) load6v(AE, S, (ks - 1) * plane, bo, e0p);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
         const int par = k & 1;
         // ---- E_0(k) sums into LDS
-        double2 e0c[6];
+        V e0c[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) e0c[q] = czero();
-        if (k < g.nz && valid) load6(AE, S, k * plane, bo, e0c);
+        for (int q = 0; q < 6; ++q) e0c[q] = vzero<V>();
+        if (k < g.nz && valid) load6v(AE, S, k * plane, bo, e0c);
+        if constexpr (P::CARRY) {
+            if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
+            if (valid && k >= 1 && k - 1 < g.nz) {
+                pol.load_e_src((k - 1) * plane, bo, rEq[0]);
+                epsq[0] = pol.load_eps((k - 1) * plane, bo);
+            }
+        }
         LE[0][0][me] = cadd(e0c[0], e0c[1]);
         LE[0][1][me] = cadd(e0c[2], e0c[3]);
         LE[0][2][me] = cadd(e0c[4], e0c[5]);
         __syncthreads();
 
-        double2 hn[T][6], en[T][6];
+        V hn[T][6], en[T][6], hns[T][3];
 #pragma unroll
         for (int s = 1; s <= T; ++s) {
             // ---- H_s at plane kh
             const int kh = k - s + 1;
-            double2 h[6];
+            V h[6], hsum[3] = {vzero<V>(), vzero<V>(), vzero<V>()};
 #pragma unroll
-            for (int q = 0; q < 6; ++q) h[q] = czero();
+            for (int q = 0; q < 6; ++q) h[q] = vzero<V>();
             if (valid && kh >= 0 && kh < g.nz) {
                 const long long po = kh * plane;
                 // old value: H_{s-1}(kh)
                 if (s == 1) {
-                    load6(A, S, po, bo, h);
+                    load6v(A, S, po, bo, h);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];
                 }
-                const double2* zp = (s == 1) ? e0p : ep[s - 1];  // E_{s-1}(kh-1)
-                ENbr nb;
+                const V* zp = (s == 1) ? e0p : ep[s - 1];  // E_{s-1}(kh-1)
+                ENbrT<V> nb;
                 nb.ex = LE[s - 1][0][me];
                 nb.ey = LE[s - 1][1][me];
                 nb.ez = LE[s - 1][2][me];
@@ -752,31 +886,51 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __rest
                 nb.ez_ym = LE[s - 1][2][ym];
                 nb.ey_xm = LE[s - 1][1][xm];
                 nb.ez_xm = LE[s - 1][2][xm];
-                double2 t[6], c[6], sa, sb;
-                cp.h(kh, po, bo, t, c, sa, sb);
-                update_h(h, t, c, sa, sb, nb);
-                if (s == T && own && kh >= k0 && kh < k1) store6(B, S, po, bo, h);
+                V t[6], c[6], src[6];
+                if constexpr (P::CARRY) {
+                    pol.hcoef_c(kh, t, c);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) src[q] = rHq[s - 1][q];
+                } else {
+                    pol.hcoef(kh, po, bo, t, c, src);
+                }
+                update_h_t<P::HMASK>(h, t, c, src, nb);
+                hsum[0] = cadd(h[0], h[1]);
+                hsum[1] = cadd(h[2], h[3]);
+                hsum[2] = cadd(h[4], h[5]);
+                if (P::H_SRC_AFTER) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h[q] = cadd(h[q], src[q]);
+                }
+                if (s == T && own && kh >= k0 && kh < k1) store6v(B, S, po, bo, h);
             }
-            const double2 hx = cadd(h[0], h[1]), hy = cadd(h[2], h[3]), hz = cadd(h[4], h[5]);
+            const V hx = hsum[0], hy = hsum[1], hz = hsum[2];
             LH[s - 1][par][0][me] = hx;
             LH[s - 1][par][1][me] = hy;
             LH[s - 1][par][2][me] = hz;
+            hns[s - 1][0] = hx;
+            hns[s - 1][1] = hy;
+            hns[s - 1][2] = hz;
 #pragma unroll
             for (int q = 0; q < 6; ++q) hn[s - 1][q] = h[q];
             // ---- E_s at plane ke (old value E_{s-1}(ke))
             const int ke = k - s;
-            double2 e[6];
+            V e[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) e[q] = czero();
+            for (int q = 0; q < 6; ++q) e[q] = vzero<V>();
             if (valid && ke >= 0 && ke < g.nz) {
                 const long long po = ke * plane;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) e[q] = (s == 1) ? e0p[q] : ep[s - 1][q];
-                HNbr nb;
+                HNbrT<V> nb;
                 if (s == T) {
                     nb.hx = hTx;
                     nb.hy = hTy;
                     nb.hz = hTz;
+                } else if constexpr (P::H_SRC_AFTER) {
+                    nb.hx = hcs[s][0];
+                    nb.hy = hcs[s][1];
+                    nb.hz = hcs[s][2];
                 } else {
                     nb.hx = cadd(hc[s][0], hc[s][1]);
                     nb.hy = cadd(hc[s][2], hc[s][3]);
@@ -788,10 +942,16 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __rest
                 nb.hz_yp = LH[s - 1][par ^ 1][2][yp];
                 nb.hy_xp = LH[s - 1][par ^ 1][1][xp];
                 nb.hz_xp = LH[s - 1][par ^ 1][2][xp];
-                double2 t[6], c[6], sa, sb;
-                cp.e(ke, po, bo, t, c, sa, sb);
-                update_e(e, t, c, sa, sb, nb);
-                if (s == T && own && ke >= k0 && ke < k1) store6(BE, S, po, bo, e);
+                V t[6], c[6], src[6];
+                if constexpr (P::CARRY) {
+                    pol.ecoef_c(ke, epsq[s - 1], t, c);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) src[q] = rEq[s - 1][q];
+                } else {
+                    pol.ecoef(ke, po, bo, t, c, src);
+                }
+                update_e_t<P::EMASK>(e, t, c, src, nb);
+                if (s == T && own && ke >= k0 && ke < k1) store6v(BE, S, po, bo, e);
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) en[s - 1][q] = e[q];
@@ -816,6 +976,18 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(CP cp, const double2* __rest
             for (int s = 1; s < T; ++s) {
                 hc[s][q] = hn[s - 1][q];
                 ep[s][q] = en[s - 1][q];
+                if (P::H_SRC_AFTER && q < 3) hcs[s][q] = hns[s - 1][q];
+            }
+        }
+        if constexpr (P::CARRY) {
+#pragma unroll
+            for (int s = T - 1; s >= 1; --s) {
+                epsq[s] = epsq[s - 1];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    rHq[s][q] = rHq[s - 1][q];
+                    rEq[s][q] = rEq[s - 1][q];
+                }
             }
         }
     }
@@ -881,6 +1053,104 @@ __global__ __launch_bounds__(256) void k_resid_final(const double* __restrict__ 
     if (threadIdx.x == 0) {
         out[0] = s1;
         out[1] = s2;
+    }
+}
+
+// Mixed-precision solver helpers.
+// k_defect_partial: r = B - A (the split residual Phi(x) - x) rounded to
+// complex64 into R, and the FP64 partial sums of ||P(B - A)||^2 and
+// ||P B||^2.
+// Where the two parts of a pair have identical coefficients -- the z pairs
+// (H_zx, H_zy), (E_zx, E_zy) everywhere, the x and y pairs on planes without a
+// PML term -- a state (v, -v) of that pair is mapped by one iteration to
+// (t v, -t v) and never reaches another field, and the physical sum P cannot
+// see it.  The correction's physical part is therefore unchanged when each
+// such pair of r is replaced by its mean, and the complex64 copy then carries
+// only the physical magnitude instead of the (non-decaying, often as large)
+// split difference.
+__global__ __launch_bounds__(256) void k_defect_partial(const double2* __restrict__ A,
+                                                        const double2* __restrict__ B,
+                                                        float2* __restrict__ R,
+                                                        const PlaneCoef* __restrict__ P,
+                                                        long long S, long long N, long long nxy,
+                                                        double* __restrict__ part) {
+    __shared__ double sh[256];
+    double r2 = 0.0, b2 = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += stride) {
+        const int k = (int)(p / nxy);
+        const PlaneCoef pc = P[k];
+        const bool hsym = pc.thz.x == pc.th0.x && pc.thz.y == pc.th0.y;
+        const bool esym = pc.sig_e == 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const double2 a0 = A[(2 * c) * S + p], a1 = A[(2 * c + 1) * S + p];
+            const double2 b0 = B[(2 * c) * S + p], b1 = B[(2 * c + 1) * S + p];
+            const double2 d0 = csub(b0, a0), d1 = csub(b1, a1);
+            const double2 d = cadd(d0, d1);
+            const bool sym = (c == 2 || c == 5) || (c < 3 ? hsym : esym);
+            if (sym) {
+                const float2 m = make_float2((float)(0.5 * d.x), (float)(0.5 * d.y));
+                R[(2 * c) * S + p] = m;
+                R[(2 * c + 1) * S + p] = m;
+            } else {
+                R[(2 * c) * S + p] = make_float2((float)d0.x, (float)d0.y);
+                R[(2 * c + 1) * S + p] = make_float2((float)d1.x, (float)d1.y);
+            }
+            const double2 pb = cadd(b0, b1);
+            r2 = __fma_rn(d.x, d.x, r2);
+            r2 = __fma_rn(d.y, d.y, r2);
+            b2 = __fma_rn(pb.x, pb.x, b2);
+            b2 = __fma_rn(pb.y, pb.y, b2);
+        }
+    }
+    const double s1 = block_sum(r2, sh);
+    const double s2 = block_sum(b2, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1;
+        part[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+// x += d (complex64 correction accumulated in FP64), all 12 arrays.
+__global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, long long S,
+                        long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double2 x = X[q * S + p];
+            const float2 d = D[q * S + p];
+            X[q * S + p] = make_double2(x.x + (double)d.x, x.y + (double)d.y);
+        }
+    }
+}
+
+// x <- a Phi(x) + b x, with a = 1/(1 - l), b = -l/(1 - l), l = e^{-iw tau}:
+// keeps the fixed point and removes every component of x that one iteration
+// only rotates by l -- the static (curl-free) fields where sigma = 0 and the
+// split differences -- which the complex64 corrections would otherwise leave
+// behind at single-precision level for ever.  Y holds Phi(x).
+__global__ void k_deflate(double2* __restrict__ X, const double2* __restrict__ Y, double2 a,
+                          double2 b, long long S, long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double2 x = X[q * S + p], y = Y[q * S + p];
+            X[q * S + p] = cadd(cmul(a, y), cmul(b, x));
+        }
+    }
+}
+
+// complex64 copy of 12 arrays (d = r starts the inner iteration)
+__global__ void k_copy32(const float2* __restrict__ src, float2* __restrict__ dst, long long S,
+                         long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) dst[q * S + p] = src[q * S + p];
     }
 }
 
@@ -971,18 +1241,33 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                       : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
 }
 
-template <class CP>
-static hipError_t blocked_impl(const CP& cp, const double2* A, double2* B, const Geo& g,
-                               int T, int rx, int ry, int kchunk, hipStream_t s) {
+template <class P>
+static hipError_t blocked_impl(const P& pol, const typename P::V* A, typename P::V* B,
+                               const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
     const int ox = rx - 2 * T, oy = ry - 2 * T;
     if (ox < 1 || oy < 1) return hipErrorInvalidValue;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
     if (T == 2 && rx == 64 && ry == 8)
-        hipLaunchKernelGGL((k_blocked<64, 8, 2, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_blocked<64, 8, 2, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
     else if (T == 2 && rx == 64 && ry == 6)
-        hipLaunchKernelGGL((k_blocked<64, 6, 2, CP>), grid, dim3(384), 0, s, cp, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_blocked<64, 6, 2, P>), grid, dim3(384), 0, s, pol, A, B, g, kchunk);
     else if (T == 2 && rx == 32 && ry == 16)
-        hipLaunchKernelGGL((k_blocked<32, 16, 2, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk);
+        hipLaunchKernelGGL((k_blocked<32, 16, 2, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <class P>
+static hipError_t blocked32_impl(const P& pol, const typename P::V* A, typename P::V* B,
+                                 const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
+    const int ox = rx - 2 * T, oy = ry - 2 * T;
+    if (ox < 1 || oy < 1) return hipErrorInvalidValue;
+    dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
+    if (T == 2 && rx == 32 && ry == 16)
+        hipLaunchKernelGGL((k_blocked<32, 16, 2, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
+    else if (T == 3 && rx == 32 && ry == 16)
+        hipLaunchKernelGGL((k_blocked<32, 16, 3, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -990,8 +1275,41 @@ static hipError_t blocked_impl(const CP& cp, const double2* A, double2* B, const
 
 hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                           int T, int rx, int ry, int kchunk, hipStream_t s) {
-    return cv.compact ? blocked_impl(compact_of(cv), A, B, g, T, rx, ry, kchunk, s)
-                      : blocked_impl(full_of(cv), A, B, g, T, rx, ry, kchunk, s);
+    if (cv.compact)
+        return blocked_impl(Pol64<CompactCoefs>{compact_of(cv)}, A, B, g, T, rx, ry, kchunk, s);
+    return blocked_impl(Pol64<FullCoefs>{full_of(cv)}, A, B, g, T, rx, ry, kchunk, s);
+}
+
+hipError_t launch_inner32(const CoefView& cv, const float2* r, const float2* A, float2* B,
+                          const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    return blocked32_impl(Pol32{compact_of(cv), r}, A, B, g, T, rx, ry, kchunk, s);
+}
+
+hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
+                         long long S, long long N, long long nxy, double* part, int nblk,
+                         double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_defect_partial, dim3(nblk), dim3(256), 0, s, A, B, R, P, S, N, nxy,
+                       part);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(double2* X, const float2* D, long long S, long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, S, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_deflate(double2* X, const double2* Y, double2 a, double2 b, long long S,
+                          long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_deflate, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, Y, a, b, S, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_copy32, dim3(grid_1d(N, 256)), dim3(256), 0, s, src, dst, S, N);
+    return hipGetLastError();
 }
 
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,

@@ -26,6 +26,7 @@ THIIM_ENOTCONV = -5
 PERIODIC, DIRICHLET = 0, 1
 KERNELS = {"auto": 0, "naive": 1, "fused": 2, "blocked": 3}
 STORAGES = {"full": 0, "compact": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
 
 SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_residual", "thiim_solve", "thiim_get_fields",
@@ -46,7 +47,7 @@ class Grid(ctypes.Structure):
                 ("kernel", ctypes.c_int), ("t_block", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
                 ("z_chunk", ctypes.c_int), ("storage", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class Coeffs(ctypes.Structure):
@@ -166,10 +167,11 @@ def thiim_destroy(ctx):
 # convenience wrapper owning the torch buffers
 # ---------------------------------------------------------------------------
 def make_grid(shape, tau=0.5, h=1.0, bcx=PERIODIC, bcy=PERIODIC, kernel="auto",
-              t_block=0, tile=(0, 0), z_chunk=0, stream=None, storage="full") -> Grid:
+              t_block=0, tile=(0, 0), z_chunk=0, stream=None, storage="full",
+              precision="fp64") -> Grid:
     nz, ny, nx = shape
     return Grid(nx, ny, nz, bcx, bcy, h, tau, KERNELS[kernel], t_block,
-                tile[0], tile[1], z_chunk, STORAGES[storage], stream)
+                tile[0], tile[1], z_chunk, STORAGES[storage], PRECISIONS[precision], stream)
 
 
 class Solver:
@@ -181,7 +183,7 @@ class Solver:
     released afterwards) or complex128 device tensors (used in place)."""
 
     def __init__(self, problem, kernel="auto", t_block=0, tile=(0, 0), z_chunk=0,
-                 device="cuda", stream=None, storage="full"):
+                 device="cuda", stream=None, storage="full", precision="fp64"):
         import torch
 
         self.torch = torch
@@ -194,7 +196,7 @@ class Solver:
         self.N = nx * ny * nz
         self.grid = make_grid(self.shape, problem.tau, problem.h, problem.bcx,
                               problem.bcy, kernel, t_block, tile, z_chunk,
-                              self.stream.cuda_stream, storage)
+                              self.stream.cuda_stream, storage, precision)
         self.ws_bytes = thiim_workspace_bytes(self.grid)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.stream(self.stream):

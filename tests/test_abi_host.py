@@ -40,7 +40,7 @@ def test_workspace_bytes_layout():
 @pytest.mark.parametrize("field,value", [("nx", 1), ("nz", 0), ("tau", 0.6), ("tau", 0.0),
                                          ("h", -1.0), ("bc_x", 2), ("kernel", 9),
                                          ("tile_x", 48), ("z_chunk", -1), ("t_block", 99),
-                                         ("storage", 2)])
+                                         ("storage", 2), ("precision", 2)])
 def test_invalid_grid_rejected(field, value):
     g = thiim.make_grid((10, 10, 10))
     setattr(g, field, value)

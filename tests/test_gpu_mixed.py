@@ -1,0 +1,85 @@
+"""GPU checks of the mixed-precision solver (complex64 inner sweeps inside
+FP64 defect correction) against the plain FP64 GPU solver and the direct
+solve of the fixed point.
+
+With x0 = 0 the first correction d = sum_j M^j r, r = Phi(0), is exactly the
+plain iterate after the same number of sweeps, so one outer step pins the
+complex64 sweep against the FP64 sweep to single-precision rounding.  After
+convergence, the FP64 residual (the kernel pinned against the oracle) must be
+below the tolerance, and the physical fields must agree with the FP64 solver
+and with the sparse-LU fixed point to the accuracy the tolerance implies."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import dense  # noqa: E402
+from paper_1510_05218_amd import inputs  # noqa: E402
+from paper_1510_05218_amd import thiim  # noqa: E402
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _phys(x):
+    x = x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+    return x[0::2] + x[1::2]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("t_block,z_chunk", [(2, 0), (3, 0), (2, 5), (3, 7)])
+def test_first_correction_equals_plain_iterates(t_block, z_chunk):
+    """Physical fields after one correction from x0 = 0 equal the plain
+    iterate (the residual's split-difference part is dropped where it cannot
+    reach the physical fields, so only P x is comparable)."""
+    _require_gpu()
+    pb = inputs.random_problem(37, 29, 23, seed=41)
+    m = 9  # one residual sweep, d = r, then ceil(8 / T) passes of T sweeps
+    passes = (m - 1 + t_block - 1) // t_block
+    n_equiv = 1 + passes * t_block
+    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=t_block,
+                     z_chunk=z_chunk)
+    rc, it, r = s.solve(1e-30, 2, m)
+    assert rc == thiim.THIIM_ENOTCONV and it == 2 + passes * t_block
+    x_mixed = _phys(s.fields())
+    f = thiim.Solver(pb, storage="compact")
+    f.iterate(n_equiv)
+    x64 = _phys(f.fields())
+    assert _rel(x_mixed, x64) < 2e-6
+
+
+def test_mixed_matches_fp64_solver():
+    _require_gpu()
+    pb = inputs.solar_cell(40, 32, 36, seed=5, npml=6, loss_range=(0.2, 0.5),
+                           eps_range=(1.0, 4.0), texture_amp=2)
+    pb.omega = 0.6
+    tol = 1e-9
+    f = thiim.Solver(pb, storage="compact")
+    rc, it64, r64 = f.solve(tol, 200000, 200)
+    assert rc == thiim.THIIM_OK and r64 <= tol
+    s = thiim.Solver(pb, storage="compact", precision="mixed")
+    rc, itm, rm = s.solve(tol, 200000, 200)
+    assert rc == thiim.THIIM_OK and rm <= tol
+    # the FP64 residual of the mixed result, recomputed from scratch
+    assert s.residual() <= tol
+    assert _rel(_phys(s.fields()), _phys(f.fields())) < 1e-6
+
+
+def test_mixed_reaches_direct_solve_fixed_point():
+    _require_gpu()
+    pb = inputs.solar_cell(6, 6, 18, seed=1, npml=6, eps_range=(1.0, 2.0),
+                           loss_range=(0.2, 0.5), texture_amp=1)
+    pb.omega = 1.0
+    xs = dense.fixed_point(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
+    s = thiim.Solver(pb, storage="compact", precision="mixed")
+    rc, it, r = s.solve(1e-11, 400000, 400)
+    assert rc == thiim.THIIM_OK and r <= 1e-11
+    assert _rel(_phys(s.fields()), oracle.physical(xs)) < 1e-7
