@@ -15,6 +15,9 @@ Contents
                      of each split pair (the physical field)
   * ``dense``     -- the time-harmonic fixed-point system assembled directly
                      from eps, sigma, omega, tau and solved by sparse LU
+  * ``adjoint``   -- the objective J = sum w eps'' |E|^2, the transposed
+                     iteration lam <- M^T lam + g (C) and the gradient of J
+                     with respect to eps' and eps''
 
 Array conventions (shared with the C-ABI of the GPU library, by definition):
   fields  : complex128 ndarray (12, nz, ny, nx), component order
@@ -56,6 +59,9 @@ def _configure(lib):
     lib.oracle_iterate.argtypes = [ctypes.c_int] * 5 + [
         ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.c_int]
     lib.oracle_iterate.restype = ctypes.c_int
+    lib.oracle_adjoint_iterate.argtypes = [ctypes.c_int] * 5 + [
+        ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.c_int]
+    lib.oracle_adjoint_iterate.restype = ctypes.c_int
     lib.oracle_flops_per_update.argtypes = [ctypes.c_int]
     lib.oracle_flops_per_update.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -178,3 +184,22 @@ def solve(coef, tol, max_it, bcx=0, bcy=0, check_every=50):
         if res <= tol:
             break
     return x, it, res
+
+
+def adjoint_iterate(coef, lam, g, n, bcx=0, bcy=0):
+    """n transposed iterations lam <- M^T lam + g in place (lam, g: (12, nz,
+    ny, nx); g may be None).  M is the linear part of one THIIM iteration."""
+    assert coef.dtype == np.complex128 and lam.dtype == np.complex128
+    assert coef.flags["C_CONTIGUOUS"] and lam.flags["C_CONTIGUOUS"]
+    _, nz, ny, nx = coef.shape
+    assert lam.shape == (12, nz, ny, nx)
+    gs = [None] * 12
+    if g is not None:
+        g = np.ascontiguousarray(g, dtype=np.complex128)
+        assert g.shape == lam.shape
+        gs = [g[i] for i in range(12)]
+    _load().oracle_adjoint_iterate(nx, ny, nz, int(bcx), int(bcy),
+                                   _ptr_array([coef[i] for i in range(28)]),
+                                   _ptr_array([lam[i] for i in range(12)]),
+                                   _ptr_array(gs), int(n))
+    return lam

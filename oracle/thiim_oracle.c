@@ -299,6 +299,92 @@ int oracle_iterate(int nx, int ny, int nz, int bcx, int bcy,
     return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Transposed iteration (gradient support).                                */
+/* ---------------------------------------------------------------------- */
+
+/* Eq. (3)/(4) make one iteration an affine map x <- M x + c, and M is the
+ * product M_E M_H of the H half-step (H parts rewritten from E) and the E
+ * half-step (E parts rewritten from the new H), so M^T = M_H^T M_E^T.
+ *
+ * A half-step rewrites each of its six parts q as
+ *     F_q(p) <- t_q(p) F_q(p) + s_q c_q(p) (G(p_hi) - G(p_lo)),
+ * with G the sum of the two split parts of the driving component,
+ * (p_hi, p_lo) = (p, p - e) for H (backward difference) and (p + e, p) for
+ * E (forward difference); a neighbour outside the domain is a ghost that
+ * contributes nothing.  Its transpose, written as a scatter: for every q and
+ * p, with u = s_q c_q(p) L_q(p) taken from the value of L_q before it is
+ * rescaled, add u to both split parts of the driving component at p_hi and
+ * subtract it at p_lo; then L_q(p) <- t_q(p) L_q(p).  The scatter writes
+ * only the other field's parts, so its order does not matter. */
+static void transpose_half(const grid_t *g, int half, const double *const *coef,
+                           double *const *L)
+{
+    for (int q = 6 * half; q < 6 * half + 6; q++) {
+        const comp_t *cm = &COMP[q];
+        const double *cq = coef[12 + q];
+        for (int k = 0; k < g->nz; k++) {
+            for (int j = 0; j < g->ny; j++) {
+                for (int i = 0; i < g->nx; i++) {
+                    long p = ((long)k * g->ny + j) * g->nx + i;
+                    double complex c = cq[2 * p] + I * cq[2 * p + 1];
+                    double complex l = L[q][2 * p] + I * L[q][2 * p + 1];
+                    double complex u = (double)cm->sign * (c * l);
+                    long hi, lo;
+                    if (half == 0) {
+                        hi = p;
+                        lo = nbr(g, k, j, i, cm->axis, -1);
+                    } else {
+                        hi = nbr(g, k, j, i, cm->axis, +1);
+                        lo = p;
+                    }
+                    const int parts[2] = {cm->g1, cm->g2};
+                    for (int m = 0; m < 2; m++) {
+                        double *G = L[parts[m]];
+                        if (hi >= 0) {
+                            G[2 * hi] += creal(u);
+                            G[2 * hi + 1] += cimag(u);
+                        }
+                        if (lo >= 0) {
+                            G[2 * lo] -= creal(u);
+                            G[2 * lo + 1] -= cimag(u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int q = 6 * half; q < 6 * half + 6; q++) {
+        const double *tq = coef[q];
+        long N = (long)g->nx * g->ny * g->nz;
+        for (long p = 0; p < N; p++) {
+            double complex t = tq[2 * p] + I * tq[2 * p + 1];
+            double complex l = L[q][2 * p] + I * L[q][2 * p + 1];
+            put(L[q], p, t * l);
+        }
+    }
+}
+
+/* n transposed iterations in place: L <- M^T L + Gs (the E half-step's
+ * transpose first, then the H half-step's), Gs = 12 arrays or NULL
+ * entries for zero. */
+int oracle_adjoint_iterate(int nx, int ny, int nz, int bcx, int bcy,
+                           const double *const *coef, double *const *L,
+                           const double *const *Gs, int n)
+{
+    grid_t g = {nx, ny, nz, bcx, bcy};
+    long N = (long)nx * ny * nz;
+    for (int it = 0; it < n; it++) {
+        transpose_half(&g, 1, coef, L);
+        transpose_half(&g, 0, coef, L);
+        for (int q = 0; q < NCOMP; q++) {
+            if (!Gs || !Gs[q]) continue;
+            for (long p = 0; p < 2 * N; p++) L[q][p] += Gs[q][p];
+        }
+    }
+    return 0;
+}
+
 /* Flop count of one component update, as written above (Listings 1/2). */
 int oracle_flops_per_update(int has_src) { return has_src ? 22 : 20; }
 

@@ -1,0 +1,140 @@
+"""Pins of the oracle's adjoint gradient (no GPU needed).
+
+  * dot-product identity <M^T u, v> = <u, M v> (bilinear, no conjugation)
+    between the transposed iteration and the forward oracle iteration with
+    zero sources (so Phi = M), for every boundary combination, with PML planes
+    and a back-iteration cell;
+  * the gradient of J = sum w eps'' |E|^2 against central finite differences
+    of J evaluated on the fixed point of the directly assembled system (the
+    sparse-LU solve of Eq. 3-5, which shares no code with the oracle's
+    iteration or its coefficient formulas), for d/deps' and d/deps'';
+  * planted mistakes in the transposed iteration fail the dot-product pin.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint, dense
+from oracle import compile as obuild
+from paper_1510_05218_amd import inputs
+
+
+def _rand(g, shape):
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def _dot_gap(pb, seed):
+    coef0 = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, {}, pb.omega, pb.tau, pb.h)
+    g = inputs.rng(seed)
+    shape = (12,) + pb.eps.shape
+    u, v = _rand(g, shape), _rand(g, shape)
+    Mv = oracle.phi(coef0, v, pb.bcx, pb.bcy)
+    MTu = oracle.adjoint_iterate(coef0, u.copy(), None, 1, pb.bcx, pb.bcy)
+    a, b = np.sum(MTu * v), np.sum(u * Mv)
+    return abs(a - b) / abs(b)
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_dot_product_identity(oracle_lib, bcx, bcy):
+    pb = inputs.random_problem(4, 5, 9, seed=3, bcx=bcx, bcy=bcy)
+    pb.eps[3, 1, 1] = -2.0 + 0.4j  # back iteration (Eq. 5)
+    assert _dot_gap(pb, 5) < 1e-14
+
+
+def test_adjoint_source_is_the_derivative_of_J(oracle_lib):
+    """g = dJ/dx: J(x + s dx) - J(x) = 2 Re(g . dx) s + O(s^2) (J is real and
+    quadratic, so the central difference is exact up to rounding)."""
+    pb = inputs.random_problem(3, 4, 6, seed=8)
+    g = inputs.rng(9)
+    x = _rand(g, (12,) + pb.eps.shape)
+    dx = _rand(g, x.shape)
+    w = g.uniform(0, 1, pb.eps.shape)
+    s = 1e-3
+    fd = (adjoint.objective(pb.eps, x + s * dx, w) - adjoint.objective(pb.eps, x - s * dx, w)) / (2 * s)
+    an = 2 * np.real(np.sum(adjoint.adjoint_source(pb.eps, x, w) * dx))
+    assert abs(fd - an) < 1e-10 * abs(an)
+
+
+def _dense_J(pb, w, eps):
+    xs = dense.fixed_point(eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h,
+                           pb.bcx, pb.bcy)
+    return adjoint.objective(eps, xs, w)
+
+
+def _check_fd(pb, w, cells, tol):
+    J, grad, _, _, _ = adjoint.gradient_of(pb, w, tol=1e-12)
+    assert abs(J - _dense_J(pb, w, pb.eps)) < 1e-11 * abs(J)
+    scale = np.abs(grad).max()
+    for c in cells:
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            hfd = 1e-6
+            ep, em = pb.eps.copy(), pb.eps.copy()
+            ep[c] += hfd * unit
+            em[c] -= hfd * unit
+            fd = (_dense_J(pb, w, ep) - _dense_J(pb, w, em)) / (2 * hfd)
+            an = grad[c].real if part == "re" else grad[c].imag
+            assert abs(fd - an) < tol * scale, (c, part, fd, an)
+
+
+@pytest.mark.parametrize("bcx,bcy,back", [(0, 0, False), (1, 1, True), (0, 1, True)])
+def test_gradient_matches_direct_solve_fd(oracle_lib, bcx, bcy, back):
+    pb = inputs.random_problem(4, 4, 10, seed=11, bcx=bcx, bcy=bcy)
+    cells = [(2, 1, 1), (5, 2, 3), (0, 0, 0), (9, 3, 2), (4, 2, 2), (1, 3, 0)]
+    if back:
+        pb.eps[4, 1, 2] = -2.5 + 0.3j
+        cells.append((4, 1, 2))
+    w = inputs.rng(12).uniform(0, 1, pb.eps.shape)
+    _check_fd(pb, w, cells, 1e-6)
+
+
+def test_gradient_dense_6cubed(oracle_lib):
+    """6 x 6 interior with 2 + 2 PML planes around 14 interior ones (the
+    direct-solve size), a layered stack with the objective on the middle
+    layer only, the x-polarised plane source."""
+    pb = inputs.solar_cell(6, 6, 18, seed=1, npml=3, n_spheres=0)
+    w = np.zeros(pb.eps.shape)
+    w[7:11] = 1.0
+    cells = [(8, 2, 3), (9, 0, 5), (7, 4, 4), (12, 1, 1), (4, 3, 2), (10, 5, 0)]
+    _check_fd(pb, w, cells, 1e-6)
+
+
+# --------------------------------------------------------------------------
+# planted mistakes in the transposed iteration
+# --------------------------------------------------------------------------
+ADJ_MUTATIONS = {
+    # the ghost / neighbour roles of the two cells of the difference swapped
+    "hi_lo": ("hi = p;\n                        lo = nbr(g, k, j, i, cm->axis, -1);",
+              "lo = p;\n                        hi = nbr(g, k, j, i, cm->axis, -1);"),
+    # the curl sign dropped
+    "sign": ("double complex u = (double)cm->sign * (c * l);", "double complex u = c * l;"),
+    # only the first split part receives the scatter
+    "one_part": ("for (int m = 0; m < 2; m++) {", "for (int m = 0; m < 1; m++) {"),
+    # half-steps transposed in the forward order
+    "order": ("transpose_half(&g, 1, coef, L);\n        transpose_half(&g, 0, coef, L);",
+              "transpose_half(&g, 0, coef, L);\n        transpose_half(&g, 1, coef, L);"),
+}
+
+
+def test_real_adjoint_passes(oracle_lib):
+    pb = inputs.random_problem(4, 5, 9, seed=3, bcx=1)
+    assert _dot_gap(pb, 5) < 1e-14
+
+
+@pytest.mark.parametrize("name", sorted(ADJ_MUTATIONS))
+def test_planted_adjoint_mistake_is_caught(oracle_lib, tmp_path, name):
+    old, new = ADJ_MUTATIONS[name]
+    src = open(obuild.SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"oracle_{name}.c"
+    path.write_text(src.replace(old, new))
+    so = obuild.compile_source(str(path), str(tmp_path / f"lib_{name}.so"))
+    saved = oracle._lib
+    oracle._lib = oracle._configure(ctypes.CDLL(os.path.abspath(so)))
+    try:
+        pb = inputs.random_problem(4, 5, 9, seed=3, bcx=1)
+        assert _dot_gap(pb, 5) > 1e-6, f"planted mistake {name} not detected"
+    finally:
+        oracle._lib = saved
