@@ -98,6 +98,8 @@ typedef struct {
     int z_chunk;      /* z planes per workgroup stream (0 = auto) */
     int storage;      /* THIIM_STORAGE_FULL or THIIM_STORAGE_COMPACT */
     int precision;    /* THIIM_PRECISION_FP64 or THIIM_PRECISION_MIXED */
+    int adjoint;      /* 1: reserve the buffers of thiim_adjoint_grad (27 more
+                       * arrays; needs THIIM_STORAGE_COMPACT), else 0 */
     void *stream;     /* hipStream_t */
 } thiim_grid;
 
@@ -150,6 +152,32 @@ int thiim_residual(thiim_ctx *ctx, double *rel_res);
  * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
 int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
                 int *iters, double *rel_res);
+
+/* Gradient of the absorption functional
+ *     J = sum_p w_p eps''_p |E_p|^2
+ * (E_p: the physical E field of the current state at cell p, each component
+ * the sum of its two split parts, Eq. (6)/(7)) with respect to eps' and
+ * eps'' of every cell, by the adjoint method.  One THIIM iteration is
+ * x <- M x + c (Sec. I-A, Eq. (3)-(5)); with g = dJ/dx and lam the solution of
+ * (I - M^T) lam = g (the transposed iteration lam <- M^T lam + g from
+ * lam = 0: the E half-step transposed, then the H half-step transposed),
+ *     dJ/dtheta_p = [theta = eps''] w_p |E_p|^2
+ *                 + 2 Re sum over the six E parts q of p of lam_q dPhi_q/dtheta_p,
+ * dPhi_q/dtheta from the closed forms of t, c and Src of the E parts (the
+ * only coefficients that depend on eps; the PML profiles are held fixed).
+ * The current state should be converged (thiim_solve); it is not changed.
+ *   weight    device, N doubles: w_p
+ *   tol > 0   iterate until ||P(lam_n - lam_{n-1})_E|| / ||P g_E|| <= tol,
+ *             checked every check_every iterations, or max_it iterations
+ *             (THIIM_ENOTCONV; the outputs are still written)
+ *   tol <= 0  exactly max_it iterations (check_every unused)
+ *   grad_eps  device, 2*N doubles: (dJ/deps', dJ/deps'') per cell
+ *   J, iters, rel_res  host, may be NULL
+ * Needs a context created with grid.adjoint = 1 (compact storage); the
+ * transposed sweep uses the fused tile and z chunk.  Synchronising. */
+int thiim_adjoint_grad(thiim_ctx *ctx, const double *weight, double tol, int max_it,
+                       int check_every, double *grad_eps, double *J, int *iters,
+                       double *rel_res);
 
 /* Device-to-device copies of the 12 split fields, one buffer of 12*2*N
  * doubles in component order.  get: synchronising. */

@@ -39,6 +39,7 @@ struct Layout {
     size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
     size_t off_a, off_b;
     size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
+    size_t off_lam, off_g;    // adjoint: 2 x 12 + 3 complex128 arrays
     size_t total;
 };
 
@@ -65,6 +66,13 @@ Layout layout_of(const thiim_grid* g) {
         off += (size_t)12 * L.S * 8;
         L.off_d32 = off;
         off += (size_t)24 * L.S * 8;
+    }
+    L.off_lam = L.off_g = 0;
+    if (g->adjoint) {
+        L.off_lam = off;
+        off += (size_t)24 * L.S * 16;
+        L.off_g = off;
+        off += (size_t)3 * L.S * 16;
     }
     L.total = off;
     return L;
@@ -95,6 +103,9 @@ int check_grid(const thiim_grid* g) {
     if ((long long)g->nx * g->ny * 16 > 0xFFFFFFFFLL)
         return fail(THIIM_EINVAL, "an x-y plane must hold fewer than 2^28 cells");
     if (g->z_chunk < 0) return fail(THIIM_EINVAL, "z_chunk must be >= 0");
+    if (g->adjoint != 0 && g->adjoint != 1) return fail(THIIM_EINVAL, "adjoint must be 0 or 1");
+    if (g->adjoint && g->storage != THIIM_STORAGE_COMPACT)
+        return fail(THIIM_EINVAL, "the adjoint gradient needs the compact coefficient storage");
     const bool tile_auto = g->tile_x == 0 && g->tile_y == 0;
     if (g->kernel == THIIM_KERNEL_BLOCKED) {
         if (!tile_auto && !(g->tile_x == 64 && (g->tile_y == 8 || g->tile_y == 6)) &&
@@ -138,6 +149,8 @@ struct thiim_ctx {
     float2* r32;                                // mixed precision buffers
     float2* d32[2];
     int inner_t, inner_rx, inner_ry, inner_chunk;
+    double2* lam[2];  // adjoint buffers
+    double2* gadj;    // adjoint source, 3 arrays
 };
 
 namespace {
@@ -199,10 +212,20 @@ hipError_t one_pass(thiim_ctx* c, int src, int dst) {
                                c->z_chunk, c->stream);
 }
 
+int reduce_pair(thiim_ctx* c, const double2* A, const double2* B, int c0, double* r2,
+                double* b2);
+
 // r2 = ||P(F[b] - F[a])||^2, b2 = ||P F[b]||^2 (synchronising)
 int reduce(thiim_ctx* c, int a, int b, double* r2, double* b2) {
-    hipError_t e = thiim::launch_resid(c->F[a], c->F[b], c->L.S, c->L.N, c->part,
-                                       kResidBlocks, c->out, c->stream);
+    return reduce_pair(c, c->F[a], c->F[b], 0, r2, b2);
+}
+
+// r2 = ||P(B - A)||^2, b2 = ||P B||^2 over physical components c0..5
+// (synchronising)
+int reduce_pair(thiim_ctx* c, const double2* A, const double2* B, int c0, double* r2,
+                double* b2) {
+    hipError_t e = thiim::launch_resid(A, B, c->L.S, c->L.N, c0, c->part, kResidBlocks, c->out,
+                                       c->stream);
     if (e != hipSuccess) return hip_fail(e, "residual launch");
     double host[2];
     e = hipMemcpyAsync(host, c->out, sizeof(host), hipMemcpyDeviceToHost, c->stream);
@@ -268,6 +291,9 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->r32 = L.off_r32 ? (float2*)(c->ws + L.off_r32) : nullptr;
     c->d32[0] = L.off_d32 ? (float2*)(c->ws + L.off_d32) : nullptr;
     c->d32[1] = L.off_d32 ? c->d32[0] + 12 * L.S : nullptr;
+    c->lam[0] = L.off_lam ? (double2*)(c->ws + L.off_lam) : nullptr;
+    c->lam[1] = L.off_lam ? c->lam[0] + 12 * L.S : nullptr;
+    c->gadj = L.off_g ? (double2*)(c->ws + L.off_g) : nullptr;
     c->cur = 0;
     c->iters = 0;
     c->geo = Geo{g->nx, g->ny, g->nz, g->bc_x, g->bc_y, L.S};
@@ -494,6 +520,85 @@ int thiim_solve(thiim_ctx* c, double tol, int max_it, int check_every, int* iter
     if (rel_res) *rel_res = r;
     if (rc) return rc;
     if (r > tol) return fail(THIIM_ENOTCONV, "iteration limit reached before tolerance");
+    return THIIM_OK;
+}
+
+int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_it,
+                       int check_every, double* grad_eps, double* J, int* iters,
+                       double* rel_res) {
+    if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
+    if (!c->lam[0]) return fail(THIIM_EINVAL, "the context was created without adjoint = 1");
+    if (!weight || !grad_eps) return fail(THIIM_EINVAL, "weight / grad_eps is NULL");
+    if (((uintptr_t)weight) % 8 || ((uintptr_t)grad_eps) % 16)
+        return fail(THIIM_EINVAL, "weight must be 8-byte and grad_eps 16-byte aligned");
+    if (max_it < 0 || (tol > 0.0 && check_every < 1) || !std::isfinite(tol))
+        return fail(THIIM_EINVAL, "need max_it >= 0, finite tol and check_every >= 1");
+    const int other = 1 - c->cur;
+    const long long S = c->L.S, N = c->L.N;
+    // Phi(x): its H parts are the H half-step of x
+    hipError_t e = one_pass(c, c->cur, other);
+    if (e != hipSuccess) return hip_fail(e, "adjoint: forward sweep");
+    e = thiim::launch_adj_source(c->F[c->cur], c->cv.eps, weight, S, N, c->gadj, c->part,
+                                 kResidBlocks, c->out, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint: source");
+    double host[2];
+    e = hipMemcpyAsync(host, c->out, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint: objective sync");
+    const double jval = host[0];
+    e = thiim::launch_fill_zero(c->lam[0], 24 * S, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint: zero");
+    int li = 0, done = 0;
+    double r = 0.0, norm0 = 0.0;
+    auto sweep = [&]() {
+        hipError_t err = thiim::launch_adjoint(c->cv, c->lam[li], c->lam[1 - li], c->gadj,
+                                               c->geo, c->tile_x, c->tile_y, c->z_chunk,
+                                               c->stream);
+        li = 1 - li;
+        ++done;
+        return err;
+    };
+    // ||P lam_E||, P the split-pair sum, of the last two iterates
+    auto measure = [&](double* rr) {
+        double r2 = 0, b2 = 0;
+        int rc = reduce_pair(c, c->lam[1 - li], c->lam[li], 3, &r2, &b2);
+        if (rc) return rc;
+        if (done == 1) norm0 = std::sqrt(b2);  // lam_1 = g
+        *rr = norm0 > 0 ? std::sqrt(r2) / norm0 : 0.0;
+        return THIIM_OK;
+    };
+    int rc = THIIM_OK;
+    if (max_it > 0) {
+        e = sweep();
+        if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
+        rc = measure(&r);
+        if (rc) return rc;
+        r = norm0 > 0 ? 1.0 : 0.0;
+    }
+    while (done < max_it && !(tol > 0.0 && r <= tol)) {
+        const int step = tol > 0.0 ? (check_every < max_it - done ? check_every : max_it - done)
+                                   : max_it - done;
+        for (int s = 0; s < step; ++s) {
+            e = sweep();
+            if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
+        }
+        rc = measure(&r);
+        if (rc) return rc;
+        if (!std::isfinite(r)) {
+            if (iters) *iters = done;
+            if (rel_res) *rel_res = r;
+            return fail(THIIM_EDIVERGED, "adjoint residual is not finite");
+        }
+    }
+    e = thiim::launch_adj_grad(c->cv, c->F[c->cur], c->F[other], c->lam[li], weight, c->geo,
+                               (double2*)grad_eps, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint: gradient");
+    if (J) *J = jval;
+    if (iters) *iters = done;
+    if (rel_res) *rel_res = r;
+    if (tol > 0.0 && r > tol)
+        return fail(THIIM_ENOTCONV, "adjoint: iteration limit reached before tolerance");
     return THIIM_OK;
 }
 

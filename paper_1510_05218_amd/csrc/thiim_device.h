@@ -133,11 +133,22 @@ __device__ __forceinline__ void update_h_t(V h[6], const V t[6], const V c[6], c
 // The six E parts (Eq. 3 / Eq. 5; the branch lives in the coefficients).
 //   E_xy: -d_z H_y   E_xz: +d_y H_z   E_yx: +d_z H_x
 //   E_yz: -d_x H_z   E_zx: -d_y H_x   E_zy: +d_x H_y
+// The signed differences s_q (G(p + e) - G(p)) of the six E parts.
+template <class V>
+__device__ __forceinline__ void e_diffs(const HNbrT<V>& h, V d[6]) {
+    d[0] = csub(h.hy, h.hy_zp);
+    d[1] = csub(h.hz_yp, h.hz);
+    d[2] = csub(h.hx_zp, h.hx);
+    d[3] = csub(h.hz, h.hz_xp);
+    d[4] = csub(h.hx, h.hx_yp);
+    d[5] = csub(h.hy_xp, h.hy);
+}
+
 template <int MASK, class V>
 __device__ __forceinline__ void update_e_t(V e[6], const V t[6], const V c[6], const V src[6],
                                            const HNbrT<V>& h) {
-    const V d[6] = {csub(h.hy, h.hy_zp), csub(h.hz_yp, h.hz), csub(h.hx_zp, h.hx),
-                    csub(h.hz, h.hz_xp), csub(h.hx, h.hx_yp), csub(h.hy_xp, h.hy)};
+    V d[6];
+    e_diffs(h, d);
 #pragma unroll
     for (int q = 0; q < 6; ++q)
         e[q] = ((MASK >> q) & 1) ? upd_src(e[q], t[q], c[q], d[q], src[q])

@@ -74,8 +74,21 @@ hipError_t launch_deflate(double2* X, const double2* Y, double2 a, double2 b, lo
                           long long N, hipStream_t s);
 hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
                          hipStream_t s);
+// ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all
+// six, 3: E only) into out[0], out[1].
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
-                        double* part, int nblk, double* out, hipStream_t s);
+                        int c0, double* part, int nblk, double* out, hipStream_t s);
+// Adjoint (compact storage): one transposed iteration A -> B with source G
+// (3 arrays); the objective / adjoint source of the state X (J in out[0]);
+// the gradient (dJ/deps', dJ/deps'') per cell.
+hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
+                          const Geo& g, int tile_x, int tile_y, int kchunk, hipStream_t s);
+hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
+                             long long N, double2* G, double* part, int nblk, double* out,
+                             hipStream_t s);
+hipError_t launch_adj_grad(const CoefView& cv, const double2* X, const double2* Y,
+                           const double2* L, const double* w, const Geo& g, double2* grad,
+                           hipStream_t s);
 hipError_t launch_fill_zero(double2* p, long long n, hipStream_t s);
 hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);
 

@@ -1011,17 +1011,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+// Physical components c0..5 (0: all, 3: E only) of A and B.
 __global__ __launch_bounds__(256) void k_resid_partial(const double2* __restrict__ A,
                                                        const double2* __restrict__ B,
-                                                       long long S, long long N,
+                                                       long long S, long long N, int c0,
                                                        double* __restrict__ part) {
     __shared__ double sh[256];
     double r2 = 0.0, b2 = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
          p += stride) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
+        for (int c = c0; c < 6; ++c) {
             const double2 a0 = A[(2 * c) * S + p], a1 = A[(2 * c + 1) * S + p];
             const double2 b0 = B[(2 * c) * S + p], b1 = B[(2 * c + 1) * S + p];
             const double2 d = cadd(csub(b0, a0), csub(b1, a1));
@@ -1053,6 +1053,349 @@ __global__ __launch_bounds__(256) void k_resid_final(const double* __restrict__ 
     if (threadIdx.x == 0) {
         out[0] = s1;
         out[1] = s2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient support).
+//
+// One THIIM iteration is x <- M x + c with M = M_E M_H (the H half-step,
+// then the E half-step), so the transposed iteration lam <- M^T lam + g
+// applies M_E^T first, then M_H^T:
+//   1. M_E^T: both parts of each physical H component b receive
+//        inc_b = sum over the two E parts q driven by b of
+//                s_q (u_q(p - e_q) - u_q(p)),   u_q = c_Eq lam_Eq,
+//      and lam_Eq <- t_Eq lam_Eq;
+//   2. M_H^T: both parts of each physical E component a receive
+//        inc_a = sum over the two H parts j driven by a of
+//                s_j (v_j(p) - v_j(p + e_j)),   v_j = c_Hj lam_Hj (after 1),
+//      and lam_Hj <- t_Hj lam_Hj;
+//   3. lam_E += g (g_a on both parts of E_a).
+// (s, e: sign and axis of the part's curl difference; neighbours outside the
+// domain are ghosts with value 0, x/y wrap when periodic.)  With the part
+// table written out (u_q, v_j of the own cell unless a shift is shown):
+//   inc_Hx =  (u2(p-z) - u2) - (u4(p-y) - u4)     E_yx: +z,  E_zx: -y
+//   inc_Hy =  (u5(p-x) - u5) - (u0(p-z) - u0)     E_zy: +x,  E_xy: -z
+//   inc_Hz =  (u1(p-y) - u1) - (u3(p-x) - u3)     E_xz: +y,  E_yz: -x
+//   inc_Ex =  (v4 - v4(p+y)) - (v2 - v2(p+z))     H_zx: +y,  H_yx: -z
+//   inc_Ey =  (v0 - v0(p+z)) - (v5 - v5(p+x))     H_xy: +z,  H_zy: -x
+//   inc_Ez =  (v3 - v3(p+x)) - (v1 - v1(p+y))     H_yz: +x,  H_xz: -y
+// Step 1 reads backward neighbours and step 2 forward neighbours of step 1's
+// output -- the dependency pattern of the forward H and E half-steps -- so
+// k_adjoint has the structure of k_fused: tile + halo ring through LDS, z
+// streamed, step 2 one plane behind step 1.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, class CP>
+__global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __restrict__ A,
+                                                    double2* __restrict__ B,
+                                                    const double2* __restrict__ G, Geo g,
+                                                    int kchunk) {
+    constexpr int NT = TX * TY;
+    constexpr int EW = TX + 2, EH = TY + 2;  // u region [-1,TX] x [-1,TY]
+    constexpr int HW = TX + 1, HH = TY + 1;  // lam_H' region [0,TX] x [0,TY]
+    constexpr int NE = EW * EH, NH = HW * HH;
+    constexpr int NHH = TX + TY + 1;
+    constexpr int NEH = NE - NT;
+    static_assert(NEH <= NT, "halo larger than tile");
+    __shared__ double2 Us[4][NE];  // u1, u3, u4, u5 of plane k
+    __shared__ double2 Vs[4][NH];  // v1, v3, v4, v5 of plane k-1
+
+    const long long S = g.S;
+    const int tid = threadIdx.x;
+    const Tile T = tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
+                           (g.nz + kchunk - 1) / kchunk);
+    const int i0 = T.bx * TX, j0 = T.by * TY;
+    const int k0 = T.bz * kchunk;
+    const int k1 = min(g.nz, k0 + kchunk);
+    const long long plane = (long long)g.nx * g.ny;
+
+    const int oi = tid % TX, oj = tid / TX;
+    const int eo = (oj + 1) * EW + (oi + 1);
+    const int ho = oj * HW + oi;
+    int gi = i0 + oi, gj = j0 + oj;
+    const bool own_store = gi < g.nx && gj < g.ny;
+    const bool own_valid = resolve_xy(g, gi, gj);
+    const uint32_t bo = own_valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
+
+    int li = 0, lj = 0;
+    if (tid < TY + 1) { li = TX; lj = tid; }
+    else if (tid < NHH) { li = tid - (TY + 1); lj = TY; }
+    else if (tid < NHH + EW) { li = tid - NHH - 1; lj = -1; }
+    else if (tid < NEH) { li = -1; lj = tid - NHH - EW; }
+    const bool has_eh = tid < NEH;
+    const bool has_hh = tid < NHH;
+    const int eh = (lj + 1) * EW + (li + 1);
+    const int hh = lj * HW + li;
+    int hgi = i0 + li, hgj = j0 + lj;
+    const bool halo_valid = has_eh && resolve_xy(g, hgi, hgj);
+    const uint32_t bh = halo_valid ? 16u * (uint32_t)(hgj * g.nx + hgi) : 0u;
+
+    const double2* AE = A + 6 * S;
+    double2* BE = B + 6 * S;
+
+    double2 ep[6], vp[6];  // own t_E lam_E and v of plane k-1
+#pragma unroll
+    for (int q = 0; q < 6; ++q) ep[q] = vp[q] = czero();
+    double2 u0m = czero(), u2m = czero();    // own u0, u2 of plane k-1
+    double2 hu0m = czero(), hu2m = czero();  // the halo cell's u0, u2 of plane k-1
+    if (k0 > 0) {
+        const long long po = (k0 - 1) * plane;
+        double2 t[6], c[6], sa, sb;
+        if (own_valid) {
+            cp.e(k0 - 1, po, bo, t, c, sa, sb);
+            u0m = cmul(c[0], ldo(AE + 0 * S + po, bo));
+            u2m = cmul(c[2], ldo(AE + 2 * S + po, bo));
+        }
+        if (has_hh && halo_valid) {
+            cp.e(k0 - 1, po, bh, t, c, sa, sb);
+            hu0m = cmul(c[0], ldo(AE + 0 * S + po, bh));
+            hu2m = cmul(c[2], ldo(AE + 2 * S + po, bh));
+        }
+    }
+
+    for (int k = k0; k <= k1; ++k) {
+        const bool plane_in = k < g.nz;
+        const long long po = k * plane;
+        double2 u[6], en[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) u[q] = en[q] = czero();
+        double2 hu0 = czero(), hu2 = czero();
+        // ---- phase 1: u = c_E lam_E of plane k; u1, u3, u4, u5 into LDS
+        if (plane_in) {
+            if (own_valid) {
+                double2 l[6], t[6], c[6], sa, sb;
+                load6(AE, S, po, bo, l);
+                cp.e(k, po, bo, t, c, sa, sb);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    u[q] = cmul(c[q], l[q]);
+                    en[q] = cmul(t[q], l[q]);
+                }
+            }
+            Us[0][eo] = u[1];
+            Us[1][eo] = u[3];
+            Us[2][eo] = u[4];
+            Us[3][eo] = u[5];
+            if (has_eh) {
+                double2 hu[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hu[q] = czero();
+                if (halo_valid) {
+                    double2 l[6], t[6], c[6], sa, sb;
+                    load6(AE, S, po, bh, l);
+                    cp.e(k, po, bh, t, c, sa, sb);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) hu[q] = cmul(c[q], l[q]);
+                }
+                Us[0][eh] = hu[1];
+                Us[1][eh] = hu[3];
+                Us[2][eh] = hu[4];
+                Us[3][eh] = hu[5];
+                hu0 = hu[0];
+                hu2 = hu[2];
+            }
+        }
+        __syncthreads();
+        // ---- phase 2: lam_H' of plane k on the tile and the +x / +y ring
+        double2 v[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = czero();
+        double2 hv1 = czero(), hv3 = czero(), hv4 = czero(), hv5 = czero();
+        if (plane_in) {
+            if (own_valid) {
+                const double2 inc[3] = {
+                    csub(csub(u2m, u[2]), csub(Us[2][eo - EW], u[4])),
+                    csub(csub(Us[3][eo - 1], u[5]), csub(u0m, u[0])),
+                    csub(csub(Us[0][eo - EW], u[1]), csub(Us[1][eo - 1], u[3]))};
+                double2 l[6], t[6], c[6], sa, sb;
+                load6(A, S, po, bo, l);
+                cp.h(k, po, bo, t, c, sa, sb);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const double2 lh = cadd(l[q], inc[q / 2]);
+                    v[q] = cmul(c[q], lh);
+                    l[q] = cmul(t[q], lh);
+                }
+                if (own_store && k < k1) store6(B, S, po, bo, l);
+            }
+            if (has_hh && halo_valid) {
+                const double2 inc[3] = {
+                    csub(csub(hu2m, hu2), csub(Us[2][eh - EW], Us[2][eh])),
+                    csub(csub(Us[3][eh - 1], Us[3][eh]), csub(hu0m, hu0)),
+                    csub(csub(Us[0][eh - EW], Us[0][eh]), csub(Us[1][eh - 1], Us[1][eh]))};
+                double2 l[6], t[6], c[6], sa, sb;
+                load6(A, S, po, bh, l);
+                cp.h(k, po, bh, t, c, sa, sb);
+                hv1 = cmul(c[1], cadd(l[1], inc[0]));
+                hv3 = cmul(c[3], cadd(l[3], inc[1]));
+                hv4 = cmul(c[4], cadd(l[4], inc[2]));
+                hv5 = cmul(c[5], cadd(l[5], inc[2]));
+            }
+        }
+        // ---- phase 3: lam_E of plane k-1 on the own cell
+        if (k > k0 && own_valid) {
+            const long long pm = po - plane;
+            double2 inc[3] = {
+                csub(csub(vp[4], Vs[2][ho + HW]), csub(vp[2], v[2])),
+                csub(csub(vp[0], v[0]), csub(vp[5], Vs[3][ho + 1])),
+                csub(csub(vp[3], Vs[1][ho + 1]), csub(vp[1], Vs[0][ho + HW]))};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) inc[a] = cadd(inc[a], ldo(G + a * S + pm, bo));
+            double2 out[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) out[q] = cadd(ep[q], inc[q / 2]);
+            if (own_store) store6(BE, S, pm, bo, out);
+        }
+        __syncthreads();
+        // ---- phase 4: v of plane k into LDS, shift the z state
+        Vs[0][ho] = v[1];
+        Vs[1][ho] = v[3];
+        Vs[2][ho] = v[4];
+        Vs[3][ho] = v[5];
+        if (has_hh) {
+            Vs[0][hh] = hv1;
+            Vs[1][hh] = hv3;
+            Vs[2][hh] = hv4;
+            Vs[3][hh] = hv5;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            vp[q] = v[q];
+            ep[q] = en[q];
+        }
+        u0m = u[0];
+        u2m = u[2];
+        hu0m = hu0;
+        hu2m = hu2;
+    }
+}
+
+// Objective J = sum w eps'' |E|^2 of the state X and the adjoint source
+// g = dJ/dx: g_a = w eps'' conj(E_a) for each physical E component a (both
+// of its parts receive it).  G: 3 arrays.  Block partial sums of J (and of
+// ||g||^2) go to part.
+__global__ __launch_bounds__(256) void k_adj_source(const double2* __restrict__ X,
+                                                    const double2* __restrict__ eps,
+                                                    const double* __restrict__ w, long long S,
+                                                    long long N, double2* __restrict__ G,
+                                                    double* __restrict__ part) {
+    __shared__ double sh[256];
+    double jsum = 0.0, g2 = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += stride) {
+        const double wp = w[p] * eps[p].y;
+        double e2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double2 E = cadd(X[(6 + 2 * a) * S + p], X[(7 + 2 * a) * S + p]);
+            e2 = __fma_rn(E.x, E.x, e2);
+            e2 = __fma_rn(E.y, E.y, e2);
+            const double2 ga = make_double2(wp * E.x, -(wp * E.y));
+            G[a * S + p] = ga;
+            g2 = __fma_rn(ga.x, ga.x, g2);
+            g2 = __fma_rn(ga.y, ga.y, g2);
+        }
+        jsum = __fma_rn(wp, e2, jsum);
+    }
+    const double s1 = block_sum(jsum, sh);
+    const double s2 = block_sum(g2, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1;
+        part[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+// dJ/deps' and dJ/deps'' per cell at the state X with adjoint L (E parts);
+// Y = Phi(X), of which only the H parts (the H half-step of X) are read.
+// Each E part q has Phi_q = t E_q + c D_q + Src_q with D_q the signed curl
+// difference of the new H sums (e_diffs), and t, c, Src all proportional to
+// 1/d, d = 1 + tau sigma / eps' (Eq. 3) or 1 - tau sigma / eps' (Eq. 5),
+// sigma = w eps'' (+ sigma_e on the z parts); c also carries 1/eps'.  Hence
+//   dPhi_q/deps'  = -(dd/deps')/d Phi_q - c D_q / eps',
+//   dPhi_q/deps'' = -(dd/deps'')/d Phi_q,
+//   dJ/dtheta     = [theta = eps''] w |E|^2 + 2 Re sum_q L_q dPhi_q/dtheta.
+__global__ __launch_bounds__(256) void k_adj_grad(CompactCoefs cp, const double2* __restrict__ X,
+                                                  const double2* __restrict__ Y,
+                                                  const double2* __restrict__ L,
+                                                  const double* __restrict__ w, Geo g,
+                                                  double2* __restrict__ grad) {
+    const long long S = g.S;
+    const long long plane = (long long)g.nx * g.ny;
+    const long long N = plane * g.nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+         p += stride) {
+        const int k = (int)(p / plane);
+        const int rem = (int)(p - k * plane);
+        const int j = rem / g.nx, i = rem - j * g.nx;
+        const long long po = k * plane;
+        const uint32_t bo = 16u * (uint32_t)rem;
+        HNbr nb;
+        nb.hx = pair_sum(Y, S, 0, po, bo);
+        nb.hy = pair_sum(Y, S, 2, po, bo);
+        nb.hz = pair_sum(Y, S, 4, po, bo);
+        nb.hx_zp = nb.hy_zp = czero();
+        if (k + 1 < g.nz) {
+            nb.hx_zp = pair_sum(Y, S, 0, po + plane, bo);
+            nb.hy_zp = pair_sum(Y, S, 2, po + plane, bo);
+        }
+        int xi = i + 1, xj = j, yi = i, yj = j + 1;
+        nb.hy_xp = nb.hz_xp = nb.hx_yp = nb.hz_yp = czero();
+        if (resolve_xy(g, xi, xj)) {
+            const uint32_t bx = 16u * (uint32_t)(xj * g.nx + xi);
+            nb.hy_xp = pair_sum(Y, S, 2, po, bx);
+            nb.hz_xp = pair_sum(Y, S, 4, po, bx);
+        }
+        if (resolve_xy(g, yi, yj)) {
+            const uint32_t by = 16u * (uint32_t)(yj * g.nx + yi);
+            nb.hx_yp = pair_sum(Y, S, 0, po, by);
+            nb.hz_yp = pair_sum(Y, S, 4, po, by);
+        }
+        double2 D[6];
+        e_diffs(nb, D);
+        const double2 eps = ldo(cp.eps + po, bo);
+        const PlaneCoef pc = cp.P[k];
+        const ECoef ec = cell_e(eps, pc.sig_e, cp.K);
+        double2 s0 = czero(), s2 = czero();
+        if (pc.has_src) {
+            s0 = ldo(cp.src + 2 * S + po, bo);
+            s2 = ldo(cp.src + 3 * S + po, bo);
+        }
+        const double inv = 1.0 / eps.x;
+        const double sgn = eps.x > 0.0 ? 1.0 : -1.0;
+        const double tau = cp.K.tau;
+        const double sg[2] = {cp.K.omega * eps.y, cp.K.omega * eps.y + pc.sig_e};
+        double a_ep[2], a_epp[2];  // (dd/dtheta) / d
+#pragma unroll
+        for (int z = 0; z < 2; ++z) {
+            const double r = 1.0 / (1.0 + sgn * tau * sg[z] * inv);
+            a_ep[z] = r * (-sgn * tau * sg[z] * inv * inv);
+            a_epp[z] = r * (sgn * tau * cp.K.omega * inv);
+        }
+        double ge = 0.0, gee = 0.0, e2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int z = (q == 0 || q == 2) ? 1 : 0;
+            const double2 t = z ? ec.t1 : ec.t0;
+            const double2 c = z ? ec.c1 : ec.c0;
+            const double2 src = q == 0 ? s0 : (q == 2 ? s2 : czero());
+            const double2 E = ldo(X + (6 + q) * S + po, bo);
+            const double2 lam = ldo(L + (6 + q) * S + po, bo);
+            const double2 cd = cmul(c, D[q]);
+            const double2 phi = cadd(cadd(cmul(t, E), cd), src);
+            const double2 dep = csub(cscale(-a_ep[z], phi), cscale(inv, cd));
+            const double2 depp = cscale(-a_epp[z], phi);
+            ge += 2.0 * (lam.x * dep.x - lam.y * dep.y);
+            gee += 2.0 * (lam.x * depp.x - lam.y * depp.y);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double2 E = cadd(ldo(X + (6 + 2 * a) * S + po, bo),
+                                   ldo(X + (7 + 2 * a) * S + po, bo));
+            e2 += E.x * E.x + E.y * E.y;
+        }
+        grad[p] = make_double2(ge, gee + w[p] * e2);
     }
 }
 
@@ -1241,6 +1584,47 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                       : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
 }
 
+hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
+                          const Geo& g, int tile_x, int tile_y, int kchunk, hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    const CompactCoefs cp = compact_of(cv);
+    dim3 grid(((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y) *
+              nchunks(g, kchunk));
+    if (tile_x == 64 && tile_y == 8)
+        hipLaunchKernelGGL((k_adjoint<64, 8, CompactCoefs>), grid, dim3(512), 0, s, cp, A, B, G,
+                           g, kchunk);
+    else if (tile_x == 32 && tile_y == 8)
+        hipLaunchKernelGGL((k_adjoint<32, 8, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B, G,
+                           g, kchunk);
+    else if (tile_x == 64 && tile_y == 4)
+        hipLaunchKernelGGL((k_adjoint<64, 4, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B, G,
+                           g, kchunk);
+    else if (tile_x == 16 && tile_y == 16)
+        hipLaunchKernelGGL((k_adjoint<16, 16, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B,
+                           G, g, kchunk);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
+                             long long N, double2* G, double* part, int nblk, double* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_source, dim3(nblk), dim3(256), 0, s, X, eps, w, S, N, G, part);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_grad(const CoefView& cv, const double2* X, const double2* Y,
+                           const double2* L, const double* w, const Geo& g, double2* grad,
+                           hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_adj_grad, dim3(grid_1d(N, 256)), dim3(256), 0, s, compact_of(cv), X,
+                       Y, L, w, g, grad);
+    return hipGetLastError();
+}
+
 template <class P>
 static hipError_t blocked_impl(const P& pol, const typename P::V* A, typename P::V* B,
                                const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
@@ -1313,8 +1697,8 @@ hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long 
 }
 
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
-                        double* part, int nblk, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid_partial, dim3(nblk), dim3(256), 0, s, A, B, S, N, part);
+                        int c0, double* part, int nblk, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid_partial, dim3(nblk), dim3(256), 0, s, A, B, S, N, c0, part);
     hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, part, nblk, out);
     return hipGetLastError();
 }

@@ -31,7 +31,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_residual", "thiim_solve", "thiim_get_fields",
            "thiim_set_fields", "thiim_get_coeffs", "thiim_iterations",
-           "thiim_destroy", "thiim_last_error", "thiim_status_str")
+           "thiim_adjoint_grad", "thiim_destroy", "thiim_last_error",
+           "thiim_status_str")
 
 
 class ThiimError(RuntimeError):
@@ -47,7 +48,8 @@ class Grid(ctypes.Structure):
                 ("kernel", ctypes.c_int), ("t_block", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
                 ("z_chunk", ctypes.c_int), ("storage", ctypes.c_int),
-                ("precision", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int), ("adjoint", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class Coeffs(ctypes.Structure):
@@ -80,6 +82,7 @@ def lib():
         L.thiim_set_fields.argtypes = [vp, vp]
         L.thiim_get_coeffs.argtypes = [vp, vp]
         L.thiim_iterations.argtypes = [vp, P(ctypes.c_longlong)]
+        L.thiim_adjoint_grad.argtypes = [vp, vp, d, i, i, vp, P(d), P(i), P(d)]
         L.thiim_destroy.argtypes = [vp]
         L.thiim_destroy.restype = None
         L.thiim_last_error.restype = ctypes.c_char_p
@@ -159,6 +162,18 @@ def thiim_iterations(ctx) -> int:
     return n.value
 
 
+def thiim_adjoint_grad(ctx, weight_ptr: int, tol: float, max_it: int, check_every: int,
+                       grad_ptr: int):
+    """Returns (status, J, iterations, rel_res); ENOTCONV is returned, not raised."""
+    J, it, r = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+    rc = lib().thiim_adjoint_grad(ctx, ctypes.c_void_p(weight_ptr), float(tol), int(max_it),
+                                  int(check_every), ctypes.c_void_p(grad_ptr), ctypes.byref(J),
+                                  ctypes.byref(it), ctypes.byref(r))
+    if rc not in (THIIM_OK, THIIM_ENOTCONV):
+        _check(rc)
+    return rc, J.value, it.value, r.value
+
+
 def thiim_destroy(ctx):
     lib().thiim_destroy(ctx)
 
@@ -168,10 +183,11 @@ def thiim_destroy(ctx):
 # ---------------------------------------------------------------------------
 def make_grid(shape, tau=0.5, h=1.0, bcx=PERIODIC, bcy=PERIODIC, kernel="auto",
               t_block=0, tile=(0, 0), z_chunk=0, stream=None, storage="full",
-              precision="fp64") -> Grid:
+              precision="fp64", adjoint=False) -> Grid:
     nz, ny, nx = shape
     return Grid(nx, ny, nz, bcx, bcy, h, tau, KERNELS[kernel], t_block,
-                tile[0], tile[1], z_chunk, STORAGES[storage], PRECISIONS[precision], stream)
+                tile[0], tile[1], z_chunk, STORAGES[storage], PRECISIONS[precision],
+                int(bool(adjoint)), stream)
 
 
 class Solver:
@@ -183,7 +199,8 @@ class Solver:
     released afterwards) or complex128 device tensors (used in place)."""
 
     def __init__(self, problem, kernel="auto", t_block=0, tile=(0, 0), z_chunk=0,
-                 device="cuda", stream=None, storage="full", precision="fp64"):
+                 device="cuda", stream=None, storage="full", precision="fp64",
+                 adjoint=False):
         import torch
 
         self.torch = torch
@@ -196,7 +213,7 @@ class Solver:
         self.N = nx * ny * nz
         self.grid = make_grid(self.shape, problem.tau, problem.h, problem.bcx,
                               problem.bcy, kernel, t_block, tile, z_chunk,
-                              self.stream.cuda_stream, storage, precision)
+                              self.stream.cuda_stream, storage, precision, adjoint)
         self.ws_bytes = thiim_workspace_bytes(self.grid)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.stream(self.stream):
@@ -231,6 +248,24 @@ class Solver:
 
     def solve(self, tol, max_it, check_every=50):
         return thiim_solve(self.ctx, tol, max_it, check_every)
+
+    def adjoint_grad(self, weight, tol=1e-10, max_it=100000, check_every=50):
+        """Gradient of J = sum w eps'' |E|^2 at the current state.  Returns
+        (status, J, grad, iterations, rel_res) with grad a complex128 tensor
+        (nz, ny, nx) holding dJ/deps' + 1j dJ/deps''."""
+        w = self._to_dev_real(weight)
+        grad = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        rc, J, it, r = thiim_adjoint_grad(self.ctx, w.data_ptr(), tol, max_it, check_every,
+                                          grad.data_ptr())
+        return rc, J, grad, it, r
+
+    def _to_dev_real(self, a):
+        if isinstance(a, self.torch.Tensor):
+            t = a.to(self.device, self.torch.float64).contiguous()
+        else:
+            t = self.torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+        assert tuple(t.shape) == self.shape
+        return t
 
     def fields(self):
         """The 12 split fields, complex128 tensor (12, nz, ny, nx) on the GPU."""

@@ -40,7 +40,7 @@ def test_workspace_bytes_layout():
 @pytest.mark.parametrize("field,value", [("nx", 1), ("nz", 0), ("tau", 0.6), ("tau", 0.0),
                                          ("h", -1.0), ("bc_x", 2), ("kernel", 9),
                                          ("tile_x", 48), ("z_chunk", -1), ("t_block", 99),
-                                         ("storage", 2), ("precision", 2)])
+                                         ("storage", 2), ("precision", 2), ("adjoint", 2)])
 def test_invalid_grid_rejected(field, value):
     g = thiim.make_grid((10, 10, 10))
     setattr(g, field, value)
@@ -48,6 +48,17 @@ def test_invalid_grid_rejected(field, value):
         thiim.thiim_workspace_bytes(g)
     assert e.value.status == thiim.THIIM_EINVAL
     assert thiim.last_error()
+
+
+def test_adjoint_workspace():
+    g = thiim.make_grid((36, 24, 24), storage="compact")
+    ga = thiim.make_grid((36, 24, 24), storage="compact", adjoint=True)
+    n = 24 * 24 * 36
+    extra = thiim.thiim_workspace_bytes(ga) - thiim.thiim_workspace_bytes(g)
+    assert abs(extra - 27 * 16 * n) < 2 ** 12  # 2 x 12 adjoint fields + 3 source arrays
+    with pytest.raises(thiim.ThiimError) as e:
+        thiim.thiim_workspace_bytes(thiim.make_grid((8, 8, 8), storage="full", adjoint=True))
+    assert e.value.status == thiim.THIIM_EINVAL
 
 
 def test_create_rejects_missing_inputs_without_device():
