@@ -145,9 +145,15 @@ int thiim_iterate(thiim_ctx *ctx, int n);
 int thiim_residual(thiim_ctx *ctx, double *rel_res);
 
 /* Iterates until thiim_residual <= tol or max_it sweeps, from the current
- * state.  FP64: the residual is checked every check_every iterations.
+ * state.  FP64: the residual is checked every check_every (>= 1) iterations.
  * MIXED: each defect-correction step is one FP64 sweep (the residual) plus
- * check_every complex64 inner sweeps (rounded up to whole blocked passes).
+ * complex64 inner sweeps d <- M d + r: check_every of them (rounded up to
+ * whole blocked passes, at least one averaging window), or, with
+ * check_every = 0, an adaptive count (doubled while a step gains less than
+ * 0.3).  The correction added to x is the mean of d over the last
+ * Kp = round(2 pi / (omega tau T)) passes of T sweeps -- one period of the
+ * modes that an iteration only rotates by e^{-i omega tau}, which the
+ * complex64 rounding would otherwise leave in x for ever.
  * *iters (sweeps done, both precisions) and *rel_res may be NULL.
  * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
 int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,

@@ -39,6 +39,7 @@ struct Layout {
     size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
     size_t off_a, off_b;
     size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
+    size_t off_ce, off_p32;   // mixed precision: per-cell float4 records, nz plane rows
     size_t off_lam, off_g;    // adjoint: 2 x 12 + 3 complex128 arrays
     size_t total;
 };
@@ -60,12 +61,16 @@ Layout layout_of(const thiim_grid* g) {
     off += (size_t)12 * L.S * 16;
     L.off_b = off;
     off += (size_t)12 * L.S * 16;
-    L.off_r32 = L.off_d32 = 0;
+    L.off_r32 = L.off_d32 = L.off_ce = L.off_p32 = 0;
     if (g->precision == THIIM_PRECISION_MIXED) {
         L.off_r32 = off;
         off += (size_t)12 * L.S * 8;
         L.off_d32 = off;
         off += (size_t)24 * L.S * 8;
+        L.off_ce = off;
+        off += (size_t)L.S * 16;
+        L.off_p32 = off;
+        off = align_up(off + sizeof(thiim::PlaneCoef32) * g->nz, kAlign);
     }
     L.off_lam = L.off_g = 0;
     if (g->adjoint) {
@@ -148,6 +153,8 @@ struct thiim_ctx {
     int t_block, region_x, region_y, bz_chunk;  // blocked sweep
     float2* r32;                                // mixed precision buffers
     float2* d32[2];
+    float4* ce32;                 // per-cell complex64 E-coefficient records
+    thiim::PlaneCoef32* p32;      // per-plane complex64 H coefficients
     int inner_t, inner_rx, inner_ry, inner_chunk;
     double2* lam[2];  // adjoint buffers
     double2* gadj;    // adjoint source, 3 arrays
@@ -291,6 +298,8 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->r32 = L.off_r32 ? (float2*)(c->ws + L.off_r32) : nullptr;
     c->d32[0] = L.off_d32 ? (float2*)(c->ws + L.off_d32) : nullptr;
     c->d32[1] = L.off_d32 ? c->d32[0] + 12 * L.S : nullptr;
+    c->ce32 = L.off_ce ? (float4*)(c->ws + L.off_ce) : nullptr;
+    c->p32 = L.off_p32 ? (thiim::PlaneCoef32*)(c->ws + L.off_p32) : nullptr;
     c->lam[0] = L.off_lam ? (double2*)(c->ws + L.off_lam) : nullptr;
     c->lam[1] = L.off_lam ? c->lam[0] + 12 * L.S : nullptr;
     c->gadj = L.off_g ? (double2*)(c->ws + L.off_g) : nullptr;
@@ -359,6 +368,11 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     if (e != hipSuccess) return bail(hip_fail(e, "create sync"));
     if (flag) return bail(fail(THIIM_EINVAL, "eps has a non-finite value or eps' == 0"));
 
+    if (c->ce32) {
+        e = thiim::launch_prep32(c->cv, c->geo, c->ce32, c->p32, c->stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "complex64 coefficient launch"));
+    }
+
     // ||P Phi(0)||: one iteration from the zero state
     e = one_pass(c, 0, 1);
     if (e != hipSuccess) return bail(hip_fail(e, "phi(0) launch"));
@@ -416,33 +430,37 @@ namespace {
 //
 // Each step: FP64 sweep Phi(x), r = Phi(x) - x (FP64 norms; complex64 copy
 // with the invisible split differences dropped), d = r then d <- M d + r in
-// complex64, x += d in FP64.  Rounding a correction to complex64 also puts
-// single-precision noise into the modes that one iteration only rotates by
-// l = e^{-iw tau} (curl-free H where sigma* = 0, curl-free E in lossless
-// cells): they never decay and hold the residual at ~1e-6.  When a step
-// gains less than kStall and kSpacing steps have passed, one FP64 step
-// x <- (Phi(x) - l x)/(1 - l) removes them (it keeps the fixed point); its
-// gain on other modes is |mu - l|/|1 - l|, hence the spacing; and if the
-// residual one correction after a deflation is above kHarm times its value
-// before it (weakly damped modes amplified, e.g. in lossless inclusions),
-// deflation stays off for the rest of the solve.
-constexpr double kStall = 0.9;
-constexpr int kSpacing = 6;
-constexpr double kHarm = 2.0;
+// complex64, x += d in FP64.
+//
+// Rounding a correction to complex64 also puts single-precision noise into
+// the modes that one iteration only rotates by l = e^{-iw tau} (curl-free H
+// where sigma* = 0, curl-free E in lossless cells).  For such a mode the
+// inner sum d = sum_k M^k r oscillates instead of converging to
+// r / (1 - l), so a correction only rotates it: left alone, the noise of all
+// corrections piles up there and holds the residual near 1e-6 |x| / |Phi(0)|.
+// The correction therefore averages d over the last Kp passes, one rotation
+// period 2 pi / (w tau) of those modes: the average of l^k over a period is
+// ~0, so the averaged d carries r / (1 - l) for them (to a factor 1/(2 Kp))
+// while every other mode mu keeps |weight| <= 1 (the average of mu^k), i.e.
+// nothing is amplified.  x accumulates the window in FP64 (x += d / Kp after
+// each of those passes).
+//
+// check_every > 0 fixes the inner sweeps per correction; 0 adapts it: start
+// at max(64, 2 Kp T) and double (up to kMaxInner) while a correction gains
+// less than kWeak.
+constexpr double kWeak = 0.3;
+constexpr int kMaxInner = 1 << 15;
 
 int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, double* rel_res) {
     const int other = 1 - c->cur;
     const int T = c->inner_t;
-    const int passes = (inner - 1 + T - 1) / T;  // inner sweeps after d = r
     const double wt = c->omega * c->g.tau;
-    const double2 lam = make_double2(std::cos(wt), -std::sin(wt));
-    const double2 den = make_double2(1.0 - lam.x, -lam.y);  // 1 - l
-    const double dd = den.x * den.x + den.y * den.y;
-    const double2 a = make_double2(den.x / dd, -den.y / dd);  // 1/(1 - l)
-    const double2 b = make_double2(-(lam.x * a.x - lam.y * a.y), -(lam.x * a.y + lam.y * a.x));
-    int done = 0, since = kSpacing;
-    double r = INFINITY, prev = INFINITY, r_defl = -1.0;
-    bool defl_on = true;
+    int Kp = (int)std::lround(2.0 * M_PI / (wt * T));
+    if (Kp < 1) Kp = 1;
+    const bool adaptive = inner <= 0;
+    int m = adaptive ? (2 * Kp * T > 64 ? 2 * Kp * T : 64) : inner;
+    int done = 0;
+    double r = INFINITY, prev = INFINITY;
     for (;;) {
         // FP64: Phi(x) into the other buffer, r = Phi(x) - x (complex64 copy)
         hipError_t e = one_pass(c, c->cur, other);
@@ -463,32 +481,24 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
             return fail(THIIM_EDIVERGED, "residual is not finite");
         }
         if (r <= tol || done >= max_it) break;
-        if (r_defl > 0.0 && since == 1) {
-            if (r > kHarm * r_defl) defl_on = false;
-            r_defl = -1.0;
-        }
-        if (defl_on && r > kStall * prev && since >= kSpacing) {
-            e = thiim::launch_deflate(c->F[c->cur], c->F[other], a, b, c->L.S, c->L.N, c->stream);
-            if (e != hipSuccess) return hip_fail(e, "mixed: deflate");
-            since = 0;
-            prev = r;
-            r_defl = r;
-            continue;
-        }
-        // complex64: d = r, then d <- M d + r
+        if (adaptive && std::isfinite(prev) && r > kWeak * prev && m < kMaxInner) m *= 2;
+        // complex64: d = r, then passes of d <- M d + r; the last Kp averaged
+        int passes = (m - 1 + T - 1) / T;
+        if (passes < Kp) passes = Kp;
         e = thiim::launch_copy32(c->r32, c->d32[0], c->L.S, c->L.N, c->stream);
         int di = 0;
         for (int p = 0; e == hipSuccess && p < passes; ++p) {
-            e = thiim::launch_inner32(c->cv, c->r32, c->d32[di], c->d32[1 - di], c->geo, T,
-                                      c->inner_rx, c->inner_ry, c->inner_chunk, c->stream);
+            e = thiim::launch_inner32(c->cv, c->ce32, c->p32, c->r32, c->d32[di],
+                                      c->d32[1 - di], c->geo, T, c->inner_rx, c->inner_ry,
+                                      c->inner_chunk, c->stream);
             di = 1 - di;
+            if (e == hipSuccess && p >= passes - Kp)
+                e = thiim::launch_accum(c->F[c->cur], c->d32[di], 1.0 / Kp, c->L.S, c->L.N,
+                                        c->stream);
         }
-        if (e == hipSuccess) e = thiim::launch_accum(c->F[c->cur], c->d32[di], c->L.S, c->L.N,
-                                                     c->stream);
         if (e != hipSuccess) return hip_fail(e, "mixed: inner sweeps");
         done += passes * T;           // sweeps run (d = r is a copy)
         c->iters += 1 + passes * T;   // equivalent plain iterations
-        since += 1;
         prev = r;
     }
     if (iters) *iters = done;
@@ -502,10 +512,13 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
 int thiim_solve(thiim_ctx* c, double tol, int max_it, int check_every, int* iters,
                 double* rel_res) {
     if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
+    if (c->g.precision == THIIM_PRECISION_MIXED) {
+        if (!(tol > 0.0) || max_it < 0 || check_every < 0)
+            return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 0");
+        return solve_mixed(c, tol, max_it, check_every, iters, rel_res);
+    }
     if (!(tol > 0.0) || max_it < 0 || check_every < 1)
         return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1");
-    if (c->g.precision == THIIM_PRECISION_MIXED)
-        return solve_mixed(c, tol, max_it, check_every, iters, rel_res);
     int done = 0;
     double r = INFINITY;
     int rc = thiim_residual(c, &r);

@@ -27,6 +27,12 @@ struct PlaneCoef {
     int pad;
 };
 
+// H coefficients of one plane rounded to complex64 (inner sweeps of the
+// mixed-precision solver).
+struct PlaneCoef32 {
+    float2 th0, thz, ch0, chz;
+};
+
 // Where the sweeps find their coefficients.
 //   full:    the 28 arrays of the paper's layout (t_q, c_q, 4 Src) at C
 //   compact: per-cell eps (1 array) + the 4 Src arrays; t, c derived on the
@@ -64,14 +70,18 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                         int tile_x, int tile_y, int kchunk, hipStream_t s);
 hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                           int T, int rx, int ry, int kchunk, hipStream_t s);
-hipError_t launch_inner32(const CoefView& cv, const float2* r, const float2* A, float2* B,
-                          const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s);
+// Mixed precision: the per-cell complex64 E-coefficient records and the
+// per-plane H table (once per context), then inner sweeps d <- M d + r.
+hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef32* P32,
+                         hipStream_t s);
+hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                          const float2* r, const float2* A, float2* B, const Geo& g, int T,
+                          int rx, int ry, int kchunk, hipStream_t s);
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
                          long long S, long long N, long long nxy, double* part, int nblk,
                          double* out, hipStream_t s);
-hipError_t launch_accum(double2* X, const float2* D, long long S, long long N, hipStream_t s);
-hipError_t launch_deflate(double2* X, const double2* Y, double2 a, double2 b, long long S,
-                          long long N, hipStream_t s);
+hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long long N,
+                        hipStream_t s);
 hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
                          hipStream_t s);
 // ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all

@@ -134,6 +134,12 @@ __device__ __forceinline__ void sto(float2* __restrict__ b, uint32_t boff16, flo
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff16 >> 1, 0, 0);
 }
+__device__ __forceinline__ float4 ldo(const float4* __restrict__ b, uint32_t boff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(b), (short)0, -1, 0x00020000), boff,
+        0, 0);
+    return __builtin_bit_cast(float4, v);
+}
 template <class V>
 __device__ __forceinline__ void load6v(const V* __restrict__ F, long long S, long long po,
                                        uint32_t bo, V v[6]) {
@@ -263,6 +269,7 @@ __global__ void k_build(BuildArgs a) {
 // (elsewhere they are exactly zero).
 // ---------------------------------------------------------------------------
 struct FullCoefs {
+    static constexpr bool COMPACT = false;
     const double2* __restrict__ C;
     const PlaneCoef* __restrict__ P;
     long long S;
@@ -297,6 +304,7 @@ struct FullCoefs {
 };
 
 struct CompactCoefs {
+    static constexpr bool COMPACT = true;
     const double2* __restrict__ eps;
     const double2* __restrict__ src;
     const PlaneCoef* __restrict__ P;
@@ -351,6 +359,8 @@ struct Pol64 {
     static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
     static constexpr bool H_SRC_AFTER = false;
     static constexpr bool CARRY = false;
+    static constexpr bool PREFETCH = false;  // measured: no gain at 250 VGPRs
+    using CRec = double2;  // unused (no carried coefficient record)
     CP cp;
     __device__ __forceinline__ void hcoef(int k, long long po, uint32_t bo, V t[6], V c[6],
                                           V src[6]) const {
@@ -370,7 +380,7 @@ struct Pol64 {
     }
 };
 
-__device__ __forceinline__ float2 to32(double2 v) {
+__host__ __device__ __forceinline__ float2 to32(double2 v) {
     return make_float2((float)v.x, (float)v.y);
 }
 
@@ -381,37 +391,48 @@ __device__ __forceinline__ float2 to32(double2 v) {
 // M d + (r_H, r_E + c_E D+ r_H)).
 struct Pol32 {
     using V = float2;
+    using CRec = float4;
     static constexpr int HMASK = 0, EMASK = SRC_MASK_ALL;
     static constexpr bool H_SRC_AFTER = true;
-    // sources and eps are loaded once, by the first stage, and handed down
-    // the stage pipeline in registers (each later stage works one plane lower)
+    // sources and the E-coefficient record are loaded once, by the first
+    // stage, and handed down the stage pipeline in registers (each later
+    // stage works one plane lower)
     static constexpr bool CARRY = true;
-    CompactCoefs cp;
-    const float2* __restrict__ r;  // 12 arrays, stride S
+    static constexpr bool PREFETCH = true;
+    const float4* __restrict__ ce;       // per-cell record (k_prep32)
+    const PlaneCoef32* __restrict__ P32;  // per-plane H coefficients
+    const float2* __restrict__ r;        // 12 arrays, stride S
+    long long S;
+    float2 ph, phc, ph2, ph2c;
     __device__ __forceinline__ void load_h_src(long long po, uint32_t bo, V src[6]) const {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) src[q] = ldo(r + q * cp.S + po, bo);
+        for (int q = 0; q < 6; ++q) src[q] = ldo(r + q * S + po, bo);
     }
     __device__ __forceinline__ void load_e_src(long long po, uint32_t bo, V src[6]) const {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) src[q] = ldo(r + (6 + q) * cp.S + po, bo);
+        for (int q = 0; q < 6; ++q) src[q] = ldo(r + (6 + q) * S + po, bo);
     }
-    __device__ __forceinline__ double2 load_eps(long long po, uint32_t bo) const {
-        return ldo(cp.eps + po, bo);
+    __device__ __forceinline__ CRec load_crec(long long po, uint32_t bo) const {
+        return ldo(ce + po, bo);
     }
     __device__ __forceinline__ void hcoef_c(int k, V t[6], V c[6]) const {
-        const PlaneCoef pc = cp.P[k];
-        const float2 tz = to32(pc.thz), t0 = to32(pc.th0), cz = to32(pc.chz), c0 = to32(pc.ch0);
-        t[0] = tz; c[0] = cz;
-        t[1] = t0; c[1] = c0;
-        t[2] = tz; c[2] = cz;
-        t[3] = t0; c[3] = c0;
-        t[4] = t0; c[4] = c0;
-        t[5] = t0; c[5] = c0;
+        const PlaneCoef32 pc = P32[k];
+        t[0] = pc.thz; c[0] = pc.chz;
+        t[1] = pc.th0; c[1] = pc.ch0;
+        t[2] = pc.thz; c[2] = pc.chz;
+        t[3] = pc.th0; c[3] = pc.ch0;
+        t[4] = pc.th0; c[4] = pc.ch0;
+        t[5] = pc.th0; c[5] = pc.ch0;
     }
-    __device__ __forceinline__ void ecoef_c(int k, double2 eps, V t[6], V c[6]) const {
-        const ECoef e = cell_e(eps, cp.P[k].sig_e, cp.K);
-        const float2 t1 = to32(e.t1), t0 = to32(e.t0), c1 = to32(e.c1), c0 = to32(e.c0);
+    // t_i = r_i P, c_i = b_i Q (see k_prep32)
+    __device__ __forceinline__ void ecoef_c(int, CRec e, V t[6], V c[6]) const {
+        const bool back = e.x < 0.0f;
+        const float2 P = back ? ph : phc, Q = back ? ph2 : ph2c;
+        const float r0 = fabsf(e.x);
+        const float2 t0 = make_float2(r0 * P.x, r0 * P.y);
+        const float2 t1 = make_float2(e.y * P.x, e.y * P.y);
+        const float2 c0 = make_float2(e.z * Q.x, e.z * Q.y);
+        const float2 c1 = make_float2(e.w * Q.x, e.w * Q.y);
         t[0] = t1; c[0] = c1;
         t[1] = t0; c[1] = c0;
         t[2] = t1; c[2] = c1;
@@ -420,6 +441,44 @@ struct Pol32 {
         t[5] = t0; c[5] = c0;
     }
 };
+
+// Coefficient data of the complex64 inner sweeps, built once per context.
+// Per cell: {+-r0, r1, b0, b1} with r_i = 1/d_i the real factor of t and c in
+// Eq. (3) (d_i = 1 + tau sigma_i / eps') or Eq. (5) (d_i = 1 - tau sigma_i /
+// eps'), i = 0 for the x/y-difference parts, 1 for the z-difference parts
+// (PML term added), and b_i = +-tau/(eps' h) r_i the real factor of c (minus
+// for Eq. 5).  Then t_i = r_i P and c_i = b_i Q, (P, Q) = (e^{-iwt},
+// e^{-iwt/2}) for eps' > 0, (e^{iwt}, e^{iwt/2}) for eps' < 0; the sign of
+// the first entry flags Eq. (5) (r0 > 0 in both cases).  Per plane: the H
+// coefficients rounded to complex64.
+__global__ void k_prep32(CompactCoefs cp, Geo g, float4* __restrict__ ce,
+                         PlaneCoef32* __restrict__ P32) {
+    const long long nxy = (long long)g.nx * g.ny;
+    const long long N = nxy * g.nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+        const int k = (int)(p / nxy);
+        const double2 eps = cp.eps[p];
+        const double sig_e = cp.P[k].sig_e;
+        const double inv = 1.0 / eps.x;
+        const double sgn = eps.x > 0.0 ? 1.0 : -1.0;
+        const double cs = cp.K.tau * inv / cp.K.h;
+        const double sg0 = cp.K.omega * eps.y;
+        const double r0 = 1.0 / (1.0 + sgn * cp.K.tau * sg0 * inv);
+        const double r1 = 1.0 / (1.0 + sgn * cp.K.tau * (sg0 + sig_e) * inv);
+        ce[p] = make_float4((float)(sgn * r0), (float)r1, (float)(sgn * cs * r0),
+                            (float)(sgn * cs * r1));
+        if (p < g.nz) {
+            const PlaneCoef pc = cp.P[p];
+            PlaneCoef32 q;
+            q.th0 = to32(pc.th0);
+            q.thz = to32(pc.thz);
+            q.ch0 = to32(pc.ch0);
+            q.chz = to32(pc.chz);
+            P32[p] = q;
+        }
+    }
+}
 
 // The 28 arrays of the full layout from compact storage, into a buffer with
 // array stride N (thiim_get_coeffs).
@@ -814,12 +873,12 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
     V ep[T][6];  // E_s parts at plane k-1-s (s = 1..T-1 used)
     V hTx = vzero<V>(), hTy = vzero<V>(), hTz = vzero<V>();  // H_T sums, plane k-T
     // CARRY policies: sources of stage s at slot s-1 (H: plane k-s+1, E: plane
-    // k-s) and eps of the E plane of stage s
+    // k-s) and the coefficient record of the E plane of stage s
     V rHq[T][6], rEq[T][6];
-    double2 epsq[T];
+    typename P::CRec crq[T];
 #pragma unroll
     for (int s = 0; s < T; ++s) {
-        epsq[s] = make_double2(1.0, 0.0);
+        crq[s] = {};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             rHq[s][q] = vzero<V>();
@@ -837,22 +896,53 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
         }
     }
     if (ks > 0 && valid) load6v(AE, S, (ks - 1) * plane, bo, e0p);
+    // The HBM reads of plane k (E_0 and H_0 parts; with CARRY also the
+    // sources and the coefficient record) are issued one step ahead, so
+    // that they are in flight while the stages of the previous plane run.
+    V e0n[6], h0n[6];
+    V rHn[6], rEn[6];
+    typename P::CRec crn = {};
+    auto prefetch = [&](int kk) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) e0n[q] = h0n[q] = vzero<V>();
+        if (valid && kk < g.nz) {
+            load6v(AE, S, kk * plane, bo, e0n);
+            load6v(A, S, kk * plane, bo, h0n);
+        }
+        if constexpr (P::CARRY) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) rHn[q] = rEn[q] = vzero<V>();
+            if (valid && kk < g.nz) pol.load_h_src(kk * plane, bo, rHn);
+            if (valid && kk >= 1 && kk - 1 < g.nz) {
+                pol.load_e_src((kk - 1) * plane, bo, rEn);
+                crn = pol.load_crec((kk - 1) * plane, bo);
+            }
+        }
+    };
+    // read-ahead costs ~48 VGPRs; taken where the carried state leaves room
+    constexpr bool PF = P::PREFETCH && T == 2;
+    if (PF) prefetch(ks);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
         const int par = k & 1;
+        if (!PF) prefetch(k);
         // ---- E_0(k) sums into LDS
-        V e0c[6];
+        V e0c[6], h0c[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) e0c[q] = vzero<V>();
-        if (k < g.nz && valid) load6v(AE, S, k * plane, bo, e0c);
-        if constexpr (P::CARRY) {
-            if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
-            if (valid && k >= 1 && k - 1 < g.nz) {
-                pol.load_e_src((k - 1) * plane, bo, rEq[0]);
-                epsq[0] = pol.load_eps((k - 1) * plane, bo);
-            }
+        for (int q = 0; q < 6; ++q) {
+            e0c[q] = e0n[q];
+            h0c[q] = h0n[q];
         }
+        if constexpr (P::CARRY) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                rHq[0][q] = rHn[q];
+                rEq[0][q] = rEn[q];
+            }
+            crq[0] = crn;
+        }
+        if (PF && k < kend) prefetch(k + 1);
         LE[0][0][me] = cadd(e0c[0], e0c[1]);
         LE[0][1][me] = cadd(e0c[2], e0c[3]);
         LE[0][2][me] = cadd(e0c[4], e0c[5]);
@@ -870,7 +960,8 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
                 const long long po = kh * plane;
                 // old value: H_{s-1}(kh)
                 if (s == 1) {
-                    load6v(A, S, po, bo, h);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h[q] = h0c[q];
                 } else {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];
@@ -944,7 +1035,7 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
                 nb.hz_xp = LH[s - 1][par ^ 1][2][xp];
                 V t[6], c[6], src[6];
                 if constexpr (P::CARRY) {
-                    pol.ecoef_c(ke, epsq[s - 1], t, c);
+                    pol.ecoef_c(ke, crq[s - 1], t, c);
 #pragma unroll
                     for (int q = 0; q < 6; ++q) src[q] = rEq[s - 1][q];
                 } else {
@@ -982,7 +1073,7 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
         if constexpr (P::CARRY) {
 #pragma unroll
             for (int s = T - 1; s >= 1; --s) {
-                epsq[s] = epsq[s - 1];
+                crq[s] = crq[s - 1];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
                     rHq[s][q] = rHq[s - 1][q];
@@ -1456,33 +1547,16 @@ __global__ __launch_bounds__(256) void k_defect_partial(const double2* __restric
     }
 }
 
-// x += d (complex64 correction accumulated in FP64), all 12 arrays.
-__global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, long long S,
-                        long long N) {
+// x += w d (complex64 correction accumulated in FP64), all 12 arrays.
+__global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, double w,
+                        long long S, long long N) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
             const double2 x = X[q * S + p];
             const float2 d = D[q * S + p];
-            X[q * S + p] = make_double2(x.x + (double)d.x, x.y + (double)d.y);
-        }
-    }
-}
-
-// x <- a Phi(x) + b x, with a = 1/(1 - l), b = -l/(1 - l), l = e^{-iw tau}:
-// keeps the fixed point and removes every component of x that one iteration
-// only rotates by l -- the static (curl-free) fields where sigma = 0 and the
-// split differences -- which the complex64 corrections would otherwise leave
-// behind at single-precision level for ever.  Y holds Phi(x).
-__global__ void k_deflate(double2* __restrict__ X, const double2* __restrict__ Y, double2 a,
-                          double2 b, long long S, long long N) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const double2 x = X[q * S + p], y = Y[q * S + p];
-            X[q * S + p] = cadd(cmul(a, y), cmul(b, x));
+            X[q * S + p] = make_double2(__fma_rn(w, (double)d.x, x.x), __fma_rn(w, (double)d.y, x.y));
         }
     }
 }
@@ -1664,10 +1738,29 @@ hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, cons
     return blocked_impl(Pol64<FullCoefs>{full_of(cv)}, A, B, g, T, rx, ry, kchunk, s);
 }
 
-hipError_t launch_inner32(const CoefView& cv, const float2* r, const float2* A, float2* B,
-                          const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
+hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef32* P32,
+                         hipStream_t s) {
     if (!cv.compact) return hipErrorInvalidValue;
-    return blocked32_impl(Pol32{compact_of(cv), r}, A, B, g, T, rx, ry, kchunk, s);
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_prep32, dim3(grid_1d(N > g.nz ? N : g.nz, 256)), dim3(256), 0, s,
+                       compact_of(cv), g, ce, P32);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                          const float2* r, const float2* A, float2* B, const Geo& g, int T,
+                          int rx, int ry, int kchunk, hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    Pol32 pol;
+    pol.ce = ce;
+    pol.P32 = P32;
+    pol.r = r;
+    pol.S = cv.S;
+    pol.ph = to32(cv.K.ph);
+    pol.phc = to32(cv.K.phc);
+    pol.ph2 = to32(cv.K.ph2);
+    pol.ph2c = to32(cv.K.ph2c);
+    return blocked32_impl(pol, A, B, g, T, rx, ry, kchunk, s);
 }
 
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
@@ -1679,14 +1772,9 @@ hipError_t launch_defect(const double2* A, const double2* B, float2* R, const Pl
     return hipGetLastError();
 }
 
-hipError_t launch_accum(double2* X, const float2* D, long long S, long long N, hipStream_t s) {
-    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, S, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_deflate(double2* X, const double2* Y, double2 a, double2 b, long long S,
-                          long long N, hipStream_t s) {
-    hipLaunchKernelGGL(k_deflate, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, Y, a, b, S, N);
+hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long long N,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, S, N);
     return hipGetLastError();
 }
 

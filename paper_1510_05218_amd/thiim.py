@@ -247,6 +247,8 @@ class Solver:
         return thiim_residual(self.ctx)
 
     def solve(self, tol, max_it, check_every=50):
+        """FP64: residual every check_every iterations.  MIXED: check_every
+        inner sweeps per correction, 0 = adaptive."""
         return thiim_solve(self.ctx, tol, max_it, check_every)
 
     def adjoint_grad(self, weight, tol=1e-10, max_it=100000, check_every=50):

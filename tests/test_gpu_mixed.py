@@ -8,6 +8,8 @@ complex64 sweep against the FP64 sweep to single-precision rounding.  After
 convergence, the FP64 residual (the kernel pinned against the oracle) must be
 below the tolerance, and the physical fields must agree with the FP64 solver
 and with the sparse-LU fixed point to the accuracy the tolerance implies."""
+import math
+
 import numpy as np
 import pytest
 
@@ -35,25 +37,36 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _window_passes(pb, T):
+    """Passes averaged per correction: one rotation period 2 pi / (w tau)."""
+    return max(1, math.floor(2 * math.pi / (pb.omega * pb.tau * T) + 0.5))
+
+
 @pytest.mark.parametrize("t_block,z_chunk", [(2, 0), (3, 0), (2, 5), (3, 7)])
 def test_first_correction_equals_plain_iterates(t_block, z_chunk):
-    """Physical fields after one correction from x0 = 0 equal the plain
-    iterate (the residual's split-difference part is dropped where it cannot
-    reach the physical fields, so only P x is comparable)."""
+    """From x0 = 0 the residual is r = Phi(0) and the inner iterate after j
+    passes is d_j = sum_{k <= jT} M^k r, the plain iterate after 1 + jT
+    iterations; one correction adds the mean of d_j over the last Kp passes.
+    Its physical fields must equal that mean of plain FP64 iterates (the
+    residual's split-difference part is dropped where it cannot reach the
+    physical fields, so only P x is comparable)."""
     _require_gpu()
     pb = inputs.random_problem(37, 29, 23, seed=41)
-    m = 9  # one residual sweep, d = r, then ceil(8 / T) passes of T sweeps
-    passes = (m - 1 + t_block - 1) // t_block
-    n_equiv = 1 + passes * t_block
-    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=t_block,
-                     z_chunk=z_chunk)
+    T = t_block
+    m = 9
+    kp = _window_passes(pb, T)
+    passes = max((m - 1 + T - 1) // T, kp)
+    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=T, z_chunk=z_chunk)
     rc, it, r = s.solve(1e-30, 2, m)
-    assert rc == thiim.THIIM_ENOTCONV and it == 2 + passes * t_block
+    assert rc == thiim.THIIM_ENOTCONV and it == 2 + passes * T
     x_mixed = _phys(s.fields())
     f = thiim.Solver(pb, storage="compact")
-    f.iterate(n_equiv)
-    x64 = _phys(f.fields())
-    assert _rel(x_mixed, x64) < 2e-6
+    f.iterate(1 + (passes - kp + 1) * T)
+    acc = _phys(f.fields()) / kp
+    for _ in range(kp - 1):
+        f.iterate(T)
+        acc = acc + _phys(f.fields()) / kp
+    assert _rel(x_mixed, acc) < 2e-6
 
 
 def test_mixed_matches_fp64_solver():
@@ -80,6 +93,6 @@ def test_mixed_reaches_direct_solve_fixed_point():
     pb.omega = 1.0
     xs = dense.fixed_point(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
     s = thiim.Solver(pb, storage="compact", precision="mixed")
-    rc, it, r = s.solve(1e-11, 400000, 400)
+    rc, it, r = s.solve(1e-11, 400000, 0)  # adaptive inner sweeps
     assert rc == thiim.THIIM_OK and r <= 1e-11
     assert _rel(_phys(s.fields()), oracle.physical(xs)) < 1e-7
