@@ -20,8 +20,14 @@ bytes per launch / average launch time measured with HIP events on the
 library's stream; ``traffic`` comes from the committed rocprofv3 counter
 summary when it was taken on the current kernel sources, else null.
 
+Context entries (not part of the timed step): the other sweep variants, the
+transposed (adjoint) sweep at the same size, and time to solution at
+relative residual 1e-8 for the plain FP64 iteration and the mixed-precision
+solver on a 128 x 128 x 256 grid of the same generator.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 512]
        [--iters 100] [--kernel blocked] [--storage compact] [--no-cpu-baseline]
+       [--no-context] [--no-adjoint] [--no-solve] [--solve-grid 128x128x256]
 """
 import argparse
 import json
@@ -54,13 +60,14 @@ BYTES_PER_LUP = {
 }
 ITERS_PER_LAUNCH = {"naive": 0.5, "fused": 1, "blocked": 2}
 SWEEP_KERNEL = {
-    ("naive", "full"): "k_naive_h<thiim::FullCoefs>",
-    ("fused", "full"): "k_fused<64, 8, thiim::FullCoefs>",
-    ("blocked", "full"): "k_blocked<64, 8, 2, thiim::FullCoefs>",
-    ("naive", "compact"): "k_naive_h<thiim::CompactCoefs>",
-    ("fused", "compact"): "k_fused<64, 8, thiim::CompactCoefs>",
-    ("blocked", "compact"): "k_blocked<32, 16, 2, thiim::CompactCoefs>",
+    ("naive", "full"): "k_naive_h<FullCoefs>",
+    ("fused", "full"): "k_fused<64,8,FullCoefs>",
+    ("blocked", "full"): "k_blocked<64,8,2,Pol64<FullCoefs>>",
+    ("naive", "compact"): "k_naive_h<CompactCoefs>",
+    ("fused", "compact"): "k_fused<64,8,CompactCoefs>",
+    ("blocked", "compact"): "k_blocked<32,16,2,Pol64<CompactCoefs>>",
 }
+ADJ_BYTES_PER_LUP = 448  # transposed sweep: 12 lam + eps + 3 g read, 12 written
 CONTEXT_VARIANTS = [("naive", "full"), ("fused", "full"), ("naive", "compact"),
                     ("fused", "compact")]
 
@@ -127,6 +134,58 @@ def cpu_baseline(pb_full, budget_s=15.0):
     }
 
 
+def adjoint_context(torch, thiim, pb, n_cells, w):
+    """Time per transposed (adjoint) iteration at the workload size: two
+    thiim_adjoint_grad calls with 10 and 30 fixed iterations; the difference
+    excludes the forward sweep, source and gradient kernels."""
+    s = thiim.Solver(pb, storage="compact", adjoint=True)
+    s.iterate(10)
+    times = {}
+    for n in (10, 30):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, J, grad, it, r = s.adjoint_grad(w, tol=0.0, max_it=n)
+        times[n] = time.perf_counter() - t
+        del grad
+    s.close()
+    ms = (times[30] - times[10]) / 20 * 1e3
+    return {"ms_per_iteration": ms, "sweep_kernel": "k_adjoint<64,8,CompactCoefs>",
+            "sweep_glups": n_cells / (ms * 1e-3) / 1e9,
+            "alg_bytes_per_lup": ADJ_BYTES_PER_LUP,
+            "alg_gbs": ADJ_BYTES_PER_LUP * n_cells / (ms * 1e-3) / 1e9}
+
+
+def solve_context(torch, thiim, inputs, shape, tol=1e-8):
+    """solves/s to relative residual tol: the plain FP64 iteration (blocked
+    sweep, residual every 500 iterations) against the mixed-precision solver
+    (complex64 inner sweeps, T = 3, adaptive inner count), same inputs."""
+    nz, ny, nx = shape
+    pb = inputs.solar_cell(nx, ny, nz, seed=10, npml=6, loss_range=(0.1, 0.5))
+    out = {"grid": f"{nx}x{ny}x{nz}", "tol": tol,
+           "workload": "solar_cell seed 10, loss in [0.1, 0.5], lambda 600 nm"}
+    fields = {}
+    for name, kw, every in (("fp64", {}, 500), ("mixed", {"precision": "mixed", "t_block": 3}, 0)):
+        s = thiim.Solver(pb, storage="compact", **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, it, r = s.solve(tol, 400000, every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        x = s.fields()
+        fields[name] = x[0::2] + x[1::2]
+        out[name] = {"status": thiim.status_str(rc), "sweeps": it, "rel_residual": r,
+                     "seconds": dt, "solves_per_s": 1.0 / dt}
+        log(f"[bench] solve {name}: {it} sweeps, residual {r:.2e}, {dt:.2f} s")
+        s.close()
+        del x
+        torch.cuda.empty_cache()
+    a, b = fields["fp64"], fields["mixed"]
+    out["mixed_vs_fp64_physical_rel_diff"] = float(torch.linalg.vector_norm(a - b) /
+                                                   torch.linalg.vector_norm(a))
+    out["speedup_solves_per_s"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
 def traffic_for(kernel_name, n_cells):
     """Counter traffic (bytes per launch) if the committed summary matches
     the current kernel sources and grid, else None."""
@@ -154,6 +213,10 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--no-context", action="store_true", help="skip the context variants")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sweep timing")
+    ap.add_argument("--no-solve", action="store_true", help="skip the 1e-8 solve comparison")
+    ap.add_argument("--solve-grid", default="128x128x256",
+                    help="nx x ny x nz of the solve comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +281,17 @@ def main():
             "alg_gbs": BYTES_PER_LUP[(k, st)] * N / (ms * 1e-3) / 1e9,
             "final_rel_residual": r,
         }
+    if not args.no_context and not args.no_adjoint:
+        log("[bench] timing the transposed (adjoint) sweep")
+        w = torch.zeros(pb.shape, dtype=torch.float64, device="cuda")
+        w[pb.shape[0] // 3: 2 * pb.shape[0] // 3] = 1.0
+        kernels["adjoint/compact"] = adjoint_context(torch, thiim, dev, N, w)
+        del w
+        torch.cuda.empty_cache()
+    solve = None
+    if not args.no_solve:
+        nx_, ny_, nz_ = (int(v) for v in args.solve_grid.split("x"))
+        solve = solve_context(torch, thiim, inputs, (nz_, ny_, nx_))
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -244,6 +318,7 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms},
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "solve_1e-8": solve,
     }
     print(json.dumps(out), flush=True)
 

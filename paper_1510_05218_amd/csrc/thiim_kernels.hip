@@ -896,9 +896,12 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
         }
     }
     if (ks > 0 && valid) load6v(AE, S, (ks - 1) * plane, bo, e0p);
-    // The HBM reads of plane k (E_0 and H_0 parts; with CARRY also the
-    // sources and the coefficient record) are issued one step ahead, so
-    // that they are in flight while the stages of the previous plane run.
+    // PF: the HBM reads of plane k (E_0 and H_0 parts; with CARRY also the
+    // sources and the coefficient record) are issued one step ahead, so that
+    // they are in flight while the stages of the previous plane run.  It
+    // costs ~48 VGPRs and is taken where the carried state leaves room and a
+    // gain was measured.
+    constexpr bool PF = P::PREFETCH && T == 2;
     V e0n[6], h0n[6];
     V rHn[6], rEn[6];
     typename P::CRec crn = {};
@@ -919,30 +922,40 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
             }
         }
     };
-    // read-ahead costs ~48 VGPRs; taken where the carried state leaves room
-    constexpr bool PF = P::PREFETCH && T == 2;
-    if (PF) prefetch(ks);
+    if constexpr (PF) prefetch(ks);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
         const int par = k & 1;
-        if (!PF) prefetch(k);
         // ---- E_0(k) sums into LDS
         V e0c[6], h0c[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            e0c[q] = e0n[q];
-            h0c[q] = h0n[q];
-        }
-        if constexpr (P::CARRY) {
+        if constexpr (PF) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                rHq[0][q] = rHn[q];
-                rEq[0][q] = rEn[q];
+                e0c[q] = e0n[q];
+                h0c[q] = h0n[q];
             }
-            crq[0] = crn;
+            if constexpr (P::CARRY) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    rHq[0][q] = rHn[q];
+                    rEq[0][q] = rEn[q];
+                }
+                crq[0] = crn;
+            }
+            if (k < kend) prefetch(k + 1);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) e0c[q] = vzero<V>();
+            if (k < g.nz && valid) load6v(AE, S, k * plane, bo, e0c);
+            if constexpr (P::CARRY) {
+                if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
+                if (valid && k >= 1 && k - 1 < g.nz) {
+                    pol.load_e_src((k - 1) * plane, bo, rEq[0]);
+                    crq[0] = pol.load_crec((k - 1) * plane, bo);
+                }
+            }
         }
-        if (PF && k < kend) prefetch(k + 1);
         LE[0][0][me] = cadd(e0c[0], e0c[1]);
         LE[0][1][me] = cadd(e0c[2], e0c[3]);
         LE[0][2][me] = cadd(e0c[4], e0c[5]);
@@ -960,8 +973,12 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
                 const long long po = kh * plane;
                 // old value: H_{s-1}(kh)
                 if (s == 1) {
+                    if constexpr (PF) {
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) h[q] = h0c[q];
+                        for (int q = 0; q < 6; ++q) h[q] = h0c[q];
+                    } else {
+                        load6v(A, S, po, bo, h);
+                    }
                 } else {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];

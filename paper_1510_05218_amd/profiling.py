@@ -24,17 +24,26 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 CALIB_BYTES = 2 ** 32  # the calibration copy reads and writes 4 GiB
 
-# algorithmic HBM bytes per cell and launch (complex128); see bench.py
+# Algorithmic HBM bytes per cell and launch (each value read or written once;
+# Src arrays only on source planes, so not counted); see bench.py.  Keys are
+# kernel names as short_name() prints them.
 ALG_BYTES_PER_CELL = {
-    "k_naive_h<thiim::FullCoefs>": 480,
-    "k_naive_e<thiim::FullCoefs>": 480,
-    "k_naive_h<thiim::CompactCoefs>": 288,
-    "k_naive_e<thiim::CompactCoefs>": 304,
-    "k_fused<64, 8, thiim::FullCoefs>": 768,
-    "k_fused<64, 8, thiim::CompactCoefs>": 400,
-    "k_blocked<64, 8, 2, thiim::FullCoefs>": 768,
-    "k_blocked<32, 16, 2, thiim::CompactCoefs>": 400,
-    "k_blocked<64, 8, 2, thiim::CompactCoefs>": 400,
+    # FP64 sweeps, complex128 (16 B per value)
+    "k_naive_h<FullCoefs>": 480,             # 12 t/c + 12 fields read, 6 written
+    "k_naive_e<FullCoefs>": 480,
+    "k_naive_h<CompactCoefs>": 288,          # 12 fields read, 6 written
+    "k_naive_e<CompactCoefs>": 304,          # + eps
+    "k_fused<64,8,FullCoefs>": 768,          # 24 t/c + 12 read, 12 written
+    "k_fused<64,8,CompactCoefs>": 400,       # eps + 12 read, 12 written
+    "k_blocked<64,8,2,Pol64<FullCoefs>>": 768,
+    "k_blocked<32,16,2,Pol64<CompactCoefs>>": 400,
+    "k_blocked<64,8,2,Pol64<CompactCoefs>>": 400,
+    # transposed sweep: 12 lam + eps + 3 g read, 12 written
+    "k_adjoint<64,8,CompactCoefs>": 448,
+    # complex64 inner sweeps (8 B per value): 12 d + 12 r + 16 B record read,
+    # 12 d written
+    "k_blocked<32,16,2,Pol32>": 304,
+    "k_blocked<32,16,3,Pol32>": 304,
 }
 
 
@@ -50,8 +59,10 @@ def source_hash() -> str:
 
 
 def short_name(kernel_name: str) -> str:
-    n = kernel_name.split("(")[0].replace("void ", "").replace("thiim::", "", 1)
-    return n.strip()
+    """'void thiim::k_blocked<32, 16, 2, thiim::Pol64<thiim::CompactCoefs> >(...)'
+    -> 'k_blocked<32,16,2,Pol64<CompactCoefs>>'."""
+    n = kernel_name.split("(")[0].replace("void ", "").replace("thiim::", "")
+    return n.replace(" ", "").strip()
 
 
 def _per_kernel(path):
@@ -77,7 +88,7 @@ def traffic_summary(fetch_csv, write_csv, n_cells, out_json, command):
     w_scale = _calibration(write, CALIB_BYTES)
     kernels = {}
     for name in sorted(set(fetch) & set(write)):
-        if not name.startswith(("k_", "thiim::k_")):
+        if not name.startswith("k_"):
             continue
         fb = sum(fetch[name]) / len(fetch[name]) / f_scale
         wb = sum(write[name]) / len(write[name]) / w_scale
