@@ -185,6 +185,62 @@ int thiim_adjoint_grad(thiim_ctx *ctx, const double *weight, double tol, int max
                        int check_every, double *grad_eps, double *J, int *iters,
                        double *rel_res);
 
+/* ---- auto-tuner ------------------------------------------------------- */
+
+/* Chosen sweep configuration. */
+typedef struct {
+    int kernel;               /* THIIM_KERNEL_FUSED or THIIM_KERNEL_BLOCKED */
+    int tile_x, tile_y;       /* fused tile or blocked region */
+    int t_block;              /* iterations per pass (1 fused, 2 blocked) */
+    int z_chunk;              /* planes per workgroup stream */
+    double ms_per_iteration;  /* measured */
+    double model_ms;          /* modelled (see below) */
+    int candidates, timed;    /* configurations considered / timed */
+} thiim_tuning;
+
+/* Picks the sweep configuration of thiim_iterate for this context: every
+ * fused tile and blocked region crossed with z chunks from 16 planes to nz
+ * is scored by a traffic / capacity model (HBM bytes per cell with tile
+ * halos and z-chunk overlap, at a bandwidth share that drops when a launch
+ * has fewer than 512 workgroups); the configurations within 1.3x of the best
+ * score (at most 8) are timed over trial_iters iterations each, from the
+ * current state into the spare buffer (the state does not advance), and the
+ * fastest is kept.  All configurations give bit-identical iterates.
+ * out may be NULL.  Synchronising. */
+int thiim_autotune(thiim_ctx *ctx, int trial_iters, thiim_tuning *out);
+
+/* ---- batches ------------------------------------------------------------ */
+
+/* A batch advances n contexts together: grids of any size (compact storage,
+ * one common stream, each context's own sweep configuration).  Contexts with
+ * the same configuration share one launch per pass, whose workgroups cover
+ * the concatenated tiles of all of them; the passes of each 64 iterations
+ * are captured once in a HIP graph and replayed (eager launches on the null
+ * stream, which cannot be captured).  A batch borrows its contexts and a
+ * small device workspace (the per-launch item tables); destroy it before
+ * them. */
+typedef struct thiim_batch thiim_batch;
+
+int thiim_batch_workspace_bytes(int n, size_t *bytes);
+int thiim_batch_create(thiim_ctx *const *ctxs, int n, void *workspace,
+                       size_t workspace_bytes, thiim_batch **out);
+
+/* n iterations of every context.  Asynchronous (uploads the item tables, a
+ * synchronising copy, when the batch changed). */
+int thiim_batch_iterate(thiim_batch *batch, int n);
+
+/* thiim_residual of every context into rel_res[n].  Synchronising. */
+int thiim_batch_residual(thiim_batch *batch, double *rel_res);
+
+/* Iterates all contexts, checking every check_every iterations, and stops
+ * advancing each one as soon as its residual is <= tol; iters[i] and
+ * rel_res[i] (may be NULL) receive its iteration count and final residual.
+ * THIIM_ENOTCONV if any context reached max_it first.  Synchronising. */
+int thiim_batch_solve(thiim_batch *batch, double tol, int max_it, int check_every,
+                      int *iters, double *rel_res);
+
+void thiim_batch_destroy(thiim_batch *batch);
+
 /* Device-to-device copies of the 12 split fields, one buffer of 12*2*N
  * doubles in component order.  get: synchronising. */
 int thiim_get_fields(thiim_ctx *ctx, double *dst);

@@ -4,8 +4,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/thiim.h"
 #include "thiim_kernels.h"
@@ -652,6 +654,450 @@ int thiim_get_coeffs(thiim_ctx* c, double* dst) {
     }
     e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? THIIM_OK : hip_fail(e, "get_coeffs sync");
+}
+
+// ---------------------------------------------------------------------------
+// Auto-tuner: a capacity / traffic model prunes the sweep configurations,
+// the survivors are timed on the live context.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Candidate {
+    int kernel, tx, ty, chunk;
+    double model_ms;
+};
+
+// Modelled time of one iteration: HBM bytes per cell (tile halos and z-chunk
+// overlap included) over the bandwidth share of the workgroups that one
+// launch keeps resident (a launch with fewer workgroups than CUs leaves the
+// rest idle).
+double model_ms(const thiim_grid& g, const Candidate& c) {
+    const double N = (double)g.nx * g.ny * g.nz;
+    const bool compact = g.storage == THIIM_STORAGE_COMPACT;
+    const double reads = compact ? 13.0 : 36.0;  // arrays read per cell and pass
+    double bytes, wgs;
+    if (c.kernel == THIIM_KERNEL_BLOCKED) {
+        const int T = 2, ox = c.tx - 2 * T, oy = c.ty - 2 * T;
+        const double halo = (double)c.tx * c.ty / ((double)ox * oy);
+        const double zover = 1.0 + (double)(T - 1) / c.chunk;
+        // full storage: every stage re-reads its 28 coefficient arrays
+        const double coef_extra = compact ? 0.0 : 28.0 * (T - 1);
+        bytes = 16.0 * ((reads * zover + coef_extra) * halo + 12.0) / T;
+        wgs = (double)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) *
+              ((g.nz + c.chunk - 1) / c.chunk);
+    } else {
+        const double nt = (double)c.tx * c.ty;
+        const double halo = 6.0 * (2.0 * c.tx + 2.0 * c.ty + 4.0) / nt;  // E parts of the ring
+        bytes = 16.0 * (reads + halo + 12.0 + 12.0 / c.chunk);
+        wgs = (double)((g.nx + c.tx - 1) / c.tx) * ((g.ny + c.ty - 1) / c.ty) *
+              ((g.nz + c.chunk - 1) / c.chunk);
+    }
+    const double fill = wgs >= 512.0 ? 1.0 : wgs / 512.0;
+    return bytes * N / (5.0e12 * fill) * 1e3;
+}
+
+void apply(thiim_ctx* c, const Candidate& k) {
+    if (k.kernel == THIIM_KERNEL_BLOCKED) {
+        c->kernel = THIIM_KERNEL_BLOCKED;
+        c->t_block = 2;
+        c->region_x = k.tx;
+        c->region_y = k.ty;
+        c->bz_chunk = k.chunk;
+    } else {
+        c->kernel = THIIM_KERNEL_FUSED;
+        c->tile_x = k.tx;
+        c->tile_y = k.ty;
+        c->z_chunk = k.chunk;
+    }
+}
+
+// One pass of the configuration from the current state into the other
+// buffer (the state does not advance).
+hipError_t trial_pass(thiim_ctx* c, const Candidate& k) {
+    const int src = c->cur, dst = 1 - c->cur;
+    if (k.kernel == THIIM_KERNEL_BLOCKED)
+        return thiim::launch_blocked(c->cv, c->F[src], c->F[dst], c->geo, 2, k.tx, k.ty, k.chunk,
+                                     c->stream);
+    return thiim::launch_fused(c->cv, c->F[src], c->F[dst], c->geo, k.tx, k.ty, k.chunk,
+                               c->stream);
+}
+
+}  // namespace
+
+int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
+    if (!c) return fail(THIIM_EINVAL, "ctx is NULL");
+    if (trial_iters < 1) return fail(THIIM_EINVAL, "trial_iters must be >= 1");
+    const thiim_grid& g = c->g;
+    std::vector<Candidate> all;
+    std::vector<int> chunks = {16, 32, 64, 128, 256, g.nz};
+    chunks.push_back(auto_chunk(g, ((g.nx + 27) / 28) * ((g.ny + 11) / 12)));
+    chunks.push_back(c->z_chunk);
+    std::sort(chunks.begin(), chunks.end());
+    chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
+    const int regions[3][2] = {{32, 16}, {64, 8}, {64, 6}};
+    const int tiles[4][2] = {{64, 8}, {32, 8}, {64, 4}, {16, 16}};
+    for (int zc : chunks) {
+        if (zc < 4 || zc > g.nz) continue;
+        for (auto& r : regions) all.push_back({THIIM_KERNEL_BLOCKED, r[0], r[1], zc, 0.0});
+        for (auto& t : tiles) all.push_back({THIIM_KERNEL_FUSED, t[0], t[1], zc, 0.0});
+    }
+    for (auto& k : all) k.model_ms = model_ms(g, k);
+    std::sort(all.begin(), all.end(),
+              [](const Candidate& a, const Candidate& b) { return a.model_ms < b.model_ms; });
+    const double cut = 1.3 * all.front().model_ms;
+    std::vector<Candidate> keep;
+    for (auto& k : all)
+        if (k.model_ms <= cut && keep.size() < 8) keep.push_back(k);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(THIIM_EDEVICE, "autotune: event create");
+    int best = -1;
+    double best_ms = INFINITY;
+    int rc = THIIM_OK;
+    for (size_t i = 0; i < keep.size() && rc == THIIM_OK; ++i) {
+        const Candidate& k = keep[i];
+        const int per = k.kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
+        const int passes = (trial_iters + per - 1) / per;
+        hipError_t e = trial_pass(c, k);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int p = 0; e == hipSuccess && p < passes; ++p) e = trial_pass(c, k);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune trial");
+            break;
+        }
+        const double per_it = ms / (passes * per);
+        if (per_it < best_ms) {
+            best_ms = per_it;
+            best = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    apply(c, keep[best]);
+    if (out) {
+        out->kernel = keep[best].kernel;
+        out->tile_x = keep[best].tx;
+        out->tile_y = keep[best].ty;
+        out->t_block = keep[best].kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
+        out->z_chunk = keep[best].chunk;
+        out->ms_per_iteration = best_ms;
+        out->model_ms = keep[best].model_ms;
+        out->candidates = (int)all.size();
+        out->timed = (int)keep.size();
+    }
+    return THIIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many contexts (uneven grids, compact storage, one stream) advanced
+// together, one batched launch per sweep configuration and pass, the passes
+// of a fixed number of iterations captured once in a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct thiim_batch {
+    struct Group {
+        int blocked;         // 1: blocked T = 2 passes, 0: fused passes
+        int tx, ty;          // region / tile
+        std::vector<int> members;
+        int total;           // tiles of all members
+        thiim::BatchItem* dev[2];  // item arrays by parity
+        int par;
+    };
+    std::vector<thiim_ctx*> ctx;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    std::vector<char> active;
+    std::vector<Group> groups;
+    bool dirty;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_iters;
+    std::vector<int> graph_par;
+};
+
+namespace {
+
+constexpr int kGraphIters = 64;  // iterations per captured graph (a multiple of 4)
+
+size_t batch_bytes(int n) { return align_up((size_t)2 * n * sizeof(thiim::BatchItem), kAlign); }
+
+void drop_graph(thiim_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+thiim::BatchItem item_of(thiim_ctx* c, int parity, int blocked, int tx, int ty, int* tiles) {
+    thiim::BatchItem it;
+    it.cv = c->cv;
+    const int src = parity ? 1 - c->cur : c->cur;
+    it.A = c->F[src];
+    it.B = c->F[1 - src];
+    it.g = c->geo;
+    const int ox = blocked ? tx - 4 : tx, oy = blocked ? ty - 4 : ty;
+    it.kchunk = blocked ? c->bz_chunk : c->z_chunk;
+    it.ntx = (c->g.nx + ox - 1) / ox;
+    it.nty = (c->g.ny + oy - 1) / oy;
+    it.ntz = (c->g.nz + it.kchunk - 1) / it.kchunk;
+    it.tile_begin = 0;
+    *tiles = it.ntx * it.nty * it.ntz;
+    return it;
+}
+
+// Groups the active problems by sweep configuration and uploads the item
+// arrays of both parities (synchronising).
+int rebuild(thiim_batch* b) {
+    drop_graph(b);
+    b->groups.clear();
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        if (!b->active[i]) continue;
+        thiim_ctx* c = b->ctx[i];
+        const int blocked = c->kernel == THIIM_KERNEL_BLOCKED && c->t_block == 2;
+        const int tx = blocked ? c->region_x : c->tile_x, ty = blocked ? c->region_y : c->tile_y;
+        auto it = std::find_if(b->groups.begin(), b->groups.end(), [&](const thiim_batch::Group& gr) {
+            return gr.blocked == blocked && gr.tx == tx && gr.ty == ty;
+        });
+        if (it == b->groups.end()) {
+            b->groups.push_back(thiim_batch::Group{blocked, tx, ty, {}, 0, {nullptr, nullptr}, 0});
+            it = b->groups.end() - 1;
+        }
+        it->members.push_back((int)i);
+    }
+    thiim::BatchItem* base = (thiim::BatchItem*)b->ws;
+    std::vector<thiim::BatchItem> host;
+    for (auto& gr : b->groups) {
+        gr.par = 0;
+        for (int par = 0; par < 2; ++par) {
+            gr.dev[par] = base + host.size();
+            int t = 0;
+            for (int m : gr.members) {
+                int tiles = 0;
+                thiim::BatchItem it = item_of(b->ctx[m], par, gr.blocked, gr.tx, gr.ty, &tiles);
+                it.tile_begin = t;
+                t += tiles;
+                host.push_back(it);
+            }
+            gr.total = t;
+        }
+    }
+    if (!host.empty()) {
+        hipError_t e = hipMemcpyAsync(b->ws, host.data(), host.size() * sizeof(thiim::BatchItem),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch: item upload");
+    }
+    b->dirty = false;
+    return THIIM_OK;
+}
+
+// Enqueues `iters` iterations of every active problem (iters even for the
+// blocked groups to stay in step; an odd remainder runs one fused pass per
+// blocked member).  Updates parities and context states.
+hipError_t enqueue(thiim_batch* b, int iters) {
+    hipError_t e = hipSuccess;
+    for (auto& gr : b->groups) {
+        const int passes = gr.blocked ? iters / 2 : iters;
+        for (int p = 0; e == hipSuccess && p < passes; ++p) {
+            e = gr.blocked ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                         gr.total, 2, gr.tx, gr.ty, b->stream)
+                           : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                       gr.total, gr.tx, gr.ty, b->stream);
+            gr.par ^= 1;
+            for (int m : gr.members) b->ctx[m]->cur ^= 1;
+        }
+        if (gr.blocked && (iters & 1)) {
+            for (int m : gr.members) {
+                thiim_ctx* c = b->ctx[m];
+                if (e == hipSuccess) e = one_pass(c, c->cur, 1 - c->cur);
+                c->cur ^= 1;
+            }
+            gr.par ^= 1;
+        }
+    }
+    return e;
+}
+
+int batch_iterate(thiim_batch* b, int n) {
+    if (b->dirty) {
+        int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    int left = n;
+    // the null stream cannot be captured: eager launches there
+    while (b->stream && left >= kGraphIters) {
+        std::vector<int> par;
+        for (auto& gr : b->groups) par.push_back(gr.par);
+        if (!b->exec || par != b->graph_par) {
+            drop_graph(b);
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "batch: begin capture");
+            hipError_t el = enqueue(b, kGraphIters);
+            e = hipStreamEndCapture(b->stream, &b->graph);
+            if (el != hipSuccess) return hip_fail(el, "batch: captured launch");
+            if (e != hipSuccess) return hip_fail(e, "batch: end capture");
+            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch: instantiate");
+            b->graph_par = par;  // kGraphIters even: parities return to `par`
+            // the capture recorded the passes without running them; the state
+            // flips it applied are undone by the even pass counts
+        }
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch: graph launch");
+        left -= kGraphIters;
+    }
+    if (left > 0) {
+        hipError_t e = enqueue(b, left);
+        if (e != hipSuccess) return hip_fail(e, "batch: launch");
+    }
+    for (size_t i = 0; i < b->ctx.size(); ++i)
+        if (b->active[i]) b->ctx[i]->iters += n;
+    return THIIM_OK;
+}
+
+// Residual of every active problem (one fused pass and reduction each, one
+// synchronisation).
+int batch_residual(thiim_batch* b, std::vector<double>& r) {
+    const size_t n = b->ctx.size();
+    std::vector<double> host(2 * n, 0.0);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        if (!b->active[i]) continue;
+        thiim_ctx* c = b->ctx[i];
+        e = one_pass(c, c->cur, 1 - c->cur);
+        if (e == hipSuccess)
+            e = thiim::launch_resid(c->F[c->cur], c->F[1 - c->cur], c->L.S, c->L.N, 0, c->part,
+                                    kResidBlocks, c->out, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&host[2 * i], c->out, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch: residual");
+    r.assign(n, NAN);
+    for (size_t i = 0; i < n; ++i) {
+        if (!b->active[i]) continue;
+        const double p0 = b->ctx[i]->phi0_norm;
+        r[i] = std::sqrt(host[2 * i]) / (p0 > 0 ? p0 : 1.0);
+    }
+    return THIIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int thiim_batch_workspace_bytes(int n, size_t* bytes) {
+    if (n < 1 || !bytes) return fail(THIIM_EINVAL, "need n >= 1 and bytes");
+    *bytes = batch_bytes(n);
+    return THIIM_OK;
+}
+
+int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t workspace_bytes,
+                       thiim_batch** out) {
+    if (!out) return fail(THIIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(THIIM_EINVAL, "need n >= 1 contexts");
+    if (!workspace || (uintptr_t)workspace % kAlign)
+        return fail(THIIM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < batch_bytes(n))
+        return fail(THIIM_ENOMEM, "workspace smaller than thiim_batch_workspace_bytes()");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(THIIM_EINVAL, "a context is NULL");
+        if (!ctxs[i]->cv.compact) return fail(THIIM_EINVAL, "batches need the compact storage");
+        if (ctxs[i]->stream != ctxs[0]->stream)
+            return fail(THIIM_EINVAL, "all contexts of a batch must use one stream");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(THIIM_EINVAL, "a context appears twice");
+    }
+    thiim_batch* b = new (std::nothrow) thiim_batch();
+    if (!b) return fail(THIIM_EINVAL, "out of host memory");
+    b->ctx.assign(ctxs, ctxs + n);
+    b->stream = ctxs[0]->stream;
+    b->ws = (char*)workspace;
+    b->ws_bytes = workspace_bytes;
+    b->active.assign(n, 1);
+    b->dirty = true;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_iters = kGraphIters;
+    *out = b;
+    return THIIM_OK;
+}
+
+int thiim_batch_iterate(thiim_batch* b, int n) {
+    if (!b || n < 0) return fail(THIIM_EINVAL, "batch is NULL or n < 0");
+    return batch_iterate(b, n);
+}
+
+int thiim_batch_residual(thiim_batch* b, double* rel_res) {
+    if (!b || !rel_res) return fail(THIIM_EINVAL, "batch / rel_res is NULL");
+    std::vector<double> r;
+    int rc = batch_residual(b, r);
+    if (rc) return rc;
+    for (size_t i = 0; i < r.size(); ++i) rel_res[i] = r[i];
+    return THIIM_OK;
+}
+
+int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, int* iters,
+                      double* rel_res) {
+    if (!b) return fail(THIIM_EINVAL, "batch is NULL");
+    if (!(tol > 0.0) || max_it < 0 || check_every < 1)
+        return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1");
+    const size_t n = b->ctx.size();
+    std::fill(b->active.begin(), b->active.end(), 1);
+    b->dirty = true;
+    std::vector<double> r(n, INFINITY);
+    std::vector<int> done(n, 0);
+    int step_done = 0, rc = THIIM_OK;
+    bool diverged = false;
+    for (;;) {
+        std::vector<double> now;
+        rc = batch_residual(b, now);
+        if (rc) break;
+        bool any = false;
+        for (size_t i = 0; i < n; ++i) {
+            if (!b->active[i]) continue;
+            r[i] = now[i];
+            done[i] = step_done;
+            if (!std::isfinite(r[i])) diverged = true;
+            if (!std::isfinite(r[i]) || r[i] <= tol) {
+                b->active[i] = 0;
+                b->dirty = true;
+            } else {
+                any = true;
+            }
+        }
+        if (!any || step_done >= max_it) break;
+        const int step = check_every < max_it - step_done ? check_every : max_it - step_done;
+        rc = batch_iterate(b, step);
+        if (rc) break;
+        step_done += step;
+    }
+    std::fill(b->active.begin(), b->active.end(), 1);
+    b->dirty = true;
+    for (size_t i = 0; i < n; ++i) {
+        if (iters) iters[i] = done[i];
+        if (rel_res) rel_res[i] = r[i];
+    }
+    if (rc) return rc;
+    if (diverged) return fail(THIIM_EDIVERGED, "batch: a residual is not finite");
+    for (size_t i = 0; i < n; ++i)
+        if (!(r[i] <= tol)) return fail(THIIM_ENOTCONV, "batch: iteration limit reached");
+    return THIIM_OK;
+}
+
+void thiim_batch_destroy(thiim_batch* b) {
+    if (!b) return;
+    drop_graph(b);
+    delete b;
 }
 
 int thiim_iterations(const thiim_ctx* c, long long* n) {

@@ -47,6 +47,19 @@ struct CoefView {
     CoefConst K;
 };
 
+// One problem of a batched pass (compact storage, FP64): its coefficient
+// view, source / destination buffers, grid, z chunk and its range in the
+// concatenated tile list (tile_begin, ntx * nty * ntz tiles).
+struct BatchItem {
+    CoefView cv;
+    const double2* A;
+    double2* B;
+    Geo g;
+    int kchunk;
+    int tile_begin;
+    int ntx, nty, ntz;
+};
+
 struct BuildArgs {
     const double2* eps_in;   // (eps', eps'') per cell
     const double* sig_e;     // nz, device
@@ -84,6 +97,12 @@ hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long
                         hipStream_t s);
 hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
                          hipStream_t s);
+// Batched passes over nitems problems whose tiles total `total` (items in
+// device memory, ordered by tile_begin).
+hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
+                              int tile_y, hipStream_t s);
+hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
+                                int ry, hipStream_t s);
 // ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all
 // six, 3: E only) into out[0], out[1].
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,

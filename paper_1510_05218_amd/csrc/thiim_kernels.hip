@@ -346,6 +346,10 @@ struct CompactCoefs {
     }
 };
 
+__host__ __device__ __forceinline__ CompactCoefs compact_view(const CoefView& v) {
+    return CompactCoefs{v.eps, v.src, v.P, v.S, v.K};
+}
+
 // Sweep policies: the complex type of the fields, the source mask, and the
 // coefficients / sources of the six H or E parts of one cell.
 //   Pol64<CP>: complex128 THIIM sweep with the paper's sources (Src of the
@@ -633,9 +637,9 @@ __global__ __launch_bounds__(256) void k_naive_e(CP cp, double2* __restrict__ F,
 // stored) so that chunks are independent.
 // ---------------------------------------------------------------------------
 template <int TX, int TY, class CP>
-__global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restrict__ A,
-                                                  double2* __restrict__ B, Geo g,
-                                                  int kchunk) {
+__device__ __forceinline__ void fused_body(const CP& cp, const double2* __restrict__ A,
+                                           double2* __restrict__ B, const Geo& g, int kchunk,
+                                           const Tile T) {
     constexpr int NT = TX * TY;
     constexpr int EW = TX + 2, EH = TY + 2;  // E region [-1,TX] x [-1,TY]
     constexpr int HW = TX + 1, HH = TY + 1;  // H region [0,TX] x [0,TY]
@@ -648,8 +652,6 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
 
     const long long S = g.S;
     const int tid = threadIdx.x;
-    const Tile T = tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
-                           (g.nz + kchunk - 1) / kchunk);
     const int i0 = T.bx * TX, j0 = T.by * TY;
     const int k0 = T.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
@@ -806,6 +808,15 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
     }
 }
 
+template <int TX, int TY, class CP>
+__global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restrict__ A,
+                                                  double2* __restrict__ B, Geo g,
+                                                  int kchunk) {
+    fused_body<TX, TY>(cp, A, B, g, kchunk,
+                       tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
+                               (g.nz + kchunk - 1) / kchunk));
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked pass: T THIIM iterations per HBM pass, A -> B.
 //
@@ -824,9 +835,9 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
 // 448 B per column per stage, with the compact storage 16 B (eps).
 // ---------------------------------------------------------------------------
 template <int RX, int RY, int T, class P>
-__global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* __restrict__ A,
-                                                    typename P::V* __restrict__ B, Geo g,
-                                                    int kchunk) {
+__device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* __restrict__ A,
+                                             typename P::V* __restrict__ B, const Geo& g,
+                                             int kchunk, const Tile TT) {
     using V = typename P::V;
     constexpr int R = RX * RY;
     constexpr int OX = RX - 2 * T, OY = RY - 2 * T;  // stored tile
@@ -837,8 +848,6 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
     const long long S = g.S;
     const long long plane = (long long)g.nx * g.ny;
     const int lane = threadIdx.x % RX, row = threadIdx.x / RX;
-    const Tile TT = tile_of((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
-                            (g.nz + kchunk - 1) / kchunk);
     const int ux = TT.bx * OX - T + lane;  // unwrapped global column
     const int uy = TT.by * OY - T + row;
     int gi = ux, gj = uy;
@@ -1100,6 +1109,64 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
         }
     }
 }
+
+template <int RX, int RY, int T, class P>
+__global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* __restrict__ A,
+                                                    typename P::V* __restrict__ B, Geo g,
+                                                    int kchunk) {
+    constexpr int OX = RX - 2 * T, OY = RY - 2 * T;
+    blocked_body<RX, RY, T>(pol, A, B, g, kchunk,
+                            tile_of((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
+                                    (g.nz + kchunk - 1) / kchunk));
+}
+
+// ---------------------------------------------------------------------------
+// Batched passes: one launch runs the fused or blocked pass of many problems
+// (grids of any size, compact storage).  The workgroups enumerate the
+// concatenated tile lists of the items; tile_of's XCD mapping applies to the
+// whole list, so each XCD receives a contiguous run of tiles (mostly of one
+// problem, sharing its L2).  A workgroup finds its item by binary search over
+// the items' first-tile indices (uniform, scalar loads).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_find(const BatchItem* __restrict__ items, int nitems,
+                                          int t) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ Tile batch_tile(const BatchItem& it, int t) {
+    const int local = t - it.tile_begin;
+    Tile TT;
+    TT.bx = local % it.ntx;
+    TT.by = (local / it.ntx) % it.nty;
+    TT.bz = local / (it.ntx * it.nty);
+    return TT;
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_fused_batch(const BatchItem* __restrict__ items,
+                                                        int nitems, int total) {
+    const Tile G = tile_of(total, 1, 1);
+    const int i = batch_find(items, nitems, G.bx);
+    const BatchItem& it = items[i];
+    fused_body<TX, TY>(compact_view(it.cv), it.A, it.B, it.g, it.kchunk, batch_tile(it, G.bx));
+}
+
+template <int RX, int RY, int T>
+__global__ __launch_bounds__(RX* RY) void k_blocked_batch(const BatchItem* __restrict__ items,
+                                                          int nitems, int total) {
+    const Tile G = tile_of(total, 1, 1);
+    const int i = batch_find(items, nitems, G.bx);
+    const BatchItem& it = items[i];
+    blocked_body<RX, RY, T>(Pol64<CompactCoefs>{compact_view(it.cv)}, it.A, it.B, it.g,
+                            it.kchunk, batch_tile(it, G.bx));
+}
+
 
 // ---------------------------------------------------------------------------
 // a5: residual.  Per cell: |P(B - A)|^2 and |P B|^2 summed over the six
@@ -1673,6 +1740,43 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                         int tile_x, int tile_y, int kchunk, hipStream_t s) {
     return cv.compact ? fused_impl(compact_of(cv), A, B, g, tile_x, tile_y, kchunk, s)
                       : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
+}
+
+hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
+                              int tile_y, hipStream_t s) {
+    if (nitems < 1 || total < 1) return hipErrorInvalidValue;
+    if (tile_x == 64 && tile_y == 8)
+        hipLaunchKernelGGL((k_fused_batch<64, 8>), dim3(total), dim3(512), 0, s, items, nitems,
+                           total);
+    else if (tile_x == 32 && tile_y == 8)
+        hipLaunchKernelGGL((k_fused_batch<32, 8>), dim3(total), dim3(256), 0, s, items, nitems,
+                           total);
+    else if (tile_x == 64 && tile_y == 4)
+        hipLaunchKernelGGL((k_fused_batch<64, 4>), dim3(total), dim3(256), 0, s, items, nitems,
+                           total);
+    else if (tile_x == 16 && tile_y == 16)
+        hipLaunchKernelGGL((k_fused_batch<16, 16>), dim3(total), dim3(256), 0, s, items, nitems,
+                           total);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
+                                int ry, hipStream_t s) {
+    if (nitems < 1 || total < 1 || T != 2) return hipErrorInvalidValue;
+    if (rx == 64 && ry == 8)
+        hipLaunchKernelGGL((k_blocked_batch<64, 8, 2>), dim3(total), dim3(512), 0, s, items,
+                           nitems, total);
+    else if (rx == 64 && ry == 6)
+        hipLaunchKernelGGL((k_blocked_batch<64, 6, 2>), dim3(total), dim3(384), 0, s, items,
+                           nitems, total);
+    else if (rx == 32 && ry == 16)
+        hipLaunchKernelGGL((k_blocked_batch<32, 16, 2>), dim3(total), dim3(512), 0, s, items,
+                           nitems, total);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,

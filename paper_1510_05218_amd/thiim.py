@@ -31,8 +31,10 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_residual", "thiim_solve", "thiim_get_fields",
            "thiim_set_fields", "thiim_get_coeffs", "thiim_iterations",
-           "thiim_adjoint_grad", "thiim_destroy", "thiim_last_error",
-           "thiim_status_str")
+           "thiim_adjoint_grad", "thiim_autotune", "thiim_batch_workspace_bytes",
+           "thiim_batch_create", "thiim_batch_iterate", "thiim_batch_residual",
+           "thiim_batch_solve", "thiim_batch_destroy", "thiim_destroy",
+           "thiim_last_error", "thiim_status_str")
 
 
 class ThiimError(RuntimeError):
@@ -50,6 +52,16 @@ class Grid(ctypes.Structure):
                 ("z_chunk", ctypes.c_int), ("storage", ctypes.c_int),
                 ("precision", ctypes.c_int), ("adjoint", ctypes.c_int),
                 ("stream", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+                ("t_block", ctypes.c_int), ("z_chunk", ctypes.c_int),
+                ("ms_per_iteration", ctypes.c_double), ("model_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int), ("timed", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Coeffs(ctypes.Structure):
@@ -83,6 +95,14 @@ def lib():
         L.thiim_get_coeffs.argtypes = [vp, vp]
         L.thiim_iterations.argtypes = [vp, P(ctypes.c_longlong)]
         L.thiim_adjoint_grad.argtypes = [vp, vp, d, i, i, vp, P(d), P(i), P(d)]
+        L.thiim_autotune.argtypes = [vp, i, P(Tuning)]
+        L.thiim_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
+        L.thiim_batch_create.argtypes = [P(vp), i, vp, ctypes.c_size_t, P(vp)]
+        L.thiim_batch_iterate.argtypes = [vp, i]
+        L.thiim_batch_residual.argtypes = [vp, P(d)]
+        L.thiim_batch_solve.argtypes = [vp, d, i, i, P(i), P(d)]
+        L.thiim_batch_destroy.argtypes = [vp]
+        L.thiim_batch_destroy.restype = None
         L.thiim_destroy.argtypes = [vp]
         L.thiim_destroy.restype = None
         L.thiim_last_error.restype = ctypes.c_char_p
@@ -174,6 +194,49 @@ def thiim_adjoint_grad(ctx, weight_ptr: int, tol: float, max_it: int, check_ever
     return rc, J.value, it.value, r.value
 
 
+def thiim_autotune(ctx, trial_iters: int = 10) -> Tuning:
+    out = Tuning()
+    _check(lib().thiim_autotune(ctx, int(trial_iters), ctypes.byref(out)))
+    return out
+
+
+def thiim_batch_workspace_bytes(n: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().thiim_batch_workspace_bytes(int(n), ctypes.byref(b)))
+    return b.value
+
+
+def thiim_batch_create(ctxs, workspace_ptr: int, workspace_bytes: int):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    out = ctypes.c_void_p()
+    _check(lib().thiim_batch_create(arr, len(ctxs), ctypes.c_void_p(workspace_ptr),
+                                    workspace_bytes, ctypes.byref(out)))
+    return out
+
+
+def thiim_batch_iterate(batch, n: int):
+    _check(lib().thiim_batch_iterate(batch, int(n)))
+
+
+def thiim_batch_residual(batch, n: int):
+    r = (ctypes.c_double * n)()
+    _check(lib().thiim_batch_residual(batch, r))
+    return np.array(r[:])
+
+
+def thiim_batch_solve(batch, n: int, tol: float, max_it: int, check_every: int = 200):
+    """Returns (status, iterations[n], rel_res[n]); ENOTCONV is returned."""
+    it, r = (ctypes.c_int * n)(), (ctypes.c_double * n)()
+    rc = lib().thiim_batch_solve(batch, float(tol), int(max_it), int(check_every), it, r)
+    if rc not in (THIIM_OK, THIIM_ENOTCONV):
+        _check(rc)
+    return rc, np.array(it[:]), np.array(r[:])
+
+
+def thiim_batch_destroy(batch):
+    lib().thiim_batch_destroy(batch)
+
+
 def thiim_destroy(ctx):
     lib().thiim_destroy(ctx)
 
@@ -251,6 +314,10 @@ class Solver:
         inner sweeps per correction, 0 = adaptive."""
         return thiim_solve(self.ctx, tol, max_it, check_every)
 
+    def autotune(self, trial_iters=10):
+        """Chooses this context's sweep configuration (thiim_autotune)."""
+        return thiim_autotune(self.ctx, trial_iters).as_dict()
+
     def adjoint_grad(self, weight, tol=1e-10, max_it=100000, check_every=50):
         """Gradient of J = sum w eps'' |E|^2 at the current state.  Returns
         (status, J, grad, iterations, rel_res) with grad a complex128 tensor
@@ -297,6 +364,54 @@ class Solver:
             thiim_destroy(self.ctx)
             self.ctx = None
             self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many problems advanced together (thiim_batch_*): ``problems`` is a list
+    of ``inputs.Problem``; each gets a compact-storage :class:`Solver` on one
+    shared non-default stream (so that the batch can capture HIP graphs),
+    optionally auto-tuned."""
+
+    def __init__(self, problems, autotune=False, trial_iters=6, device="cuda", stream=None,
+                 **solver_kw):
+        import torch
+
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.solvers = [Solver(p, storage="compact", device=device, stream=self.stream,
+                               **solver_kw) for p in problems]
+        self.tuning = [s.autotune(trial_iters) if autotune else None for s in self.solvers]
+        self.n = len(self.solvers)
+        self.ws_bytes = thiim_batch_workspace_bytes(self.n)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.batch = thiim_batch_create([s.ctx for s in self.solvers],
+                                        self.workspace.data_ptr(), self.ws_bytes)
+
+    def iterate(self, n):
+        thiim_batch_iterate(self.batch, n)
+
+    def residual(self):
+        return thiim_batch_residual(self.batch, self.n)
+
+    def solve(self, tol, max_it, check_every=200):
+        return thiim_batch_solve(self.batch, self.n, tol, max_it, check_every)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "batch", None) is not None:
+            thiim_batch_destroy(self.batch)
+            self.batch = None
+        for s in getattr(self, "solvers", []):
+            s.close()
+        self.solvers = []
 
     def __del__(self):
         try:

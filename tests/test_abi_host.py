@@ -61,6 +61,15 @@ def test_adjoint_workspace():
     assert e.value.status == thiim.THIIM_EINVAL
 
 
+def test_batch_workspace_bytes():
+    b1 = thiim.thiim_batch_workspace_bytes(1)
+    b100 = thiim.thiim_batch_workspace_bytes(100)
+    assert b1 >= 256 and b100 > b1 and b100 % 256 == 0
+    with pytest.raises(thiim.ThiimError) as e:
+        thiim.thiim_batch_workspace_bytes(0)
+    assert e.value.status == thiim.THIIM_EINVAL
+
+
 def test_create_rejects_missing_inputs_without_device():
     g = thiim.make_grid((8, 8, 8))
     with pytest.raises(thiim.ThiimError) as e:
