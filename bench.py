@@ -21,13 +21,16 @@ library's stream; ``traffic`` comes from the committed rocprofv3 counter
 summary when it was taken on the current kernel sources, else null.
 
 Context entries (not part of the timed step): the other sweep variants, the
-transposed (adjoint) sweep at the same size, and time to solution at
-relative residual 1e-8 for the plain FP64 iteration and the mixed-precision
-solver on a 128 x 128 x 256 grid of the same generator.
+transposed (adjoint) sweep at the same size, time to solution at relative
+residual 1e-8 for the plain FP64 iteration and the mixed-precision solver on
+a 128 x 128 x 256 grid of the same generator, and a batched spectral sweep
+(4 wavelengths x 2 geometries: batched against one-by-one throughput, and
+the batched mixed solver against plain FP64 solves in solves/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 512]
        [--iters 100] [--kernel blocked] [--storage compact] [--no-cpu-baseline]
        [--no-context] [--no-adjoint] [--no-solve] [--solve-grid 128x128x256]
+       [--no-spectral]
 """
 import argparse
 import json
@@ -186,6 +189,72 @@ def solve_context(torch, thiim, inputs, shape, tol=1e-8):
     return out
 
 
+def spectral_context(torch, thiim, inputs, tol=1e-8):
+    """A small spectral sweep: 4 wavelengths (300-1100 nm) x 2 textured
+    geometries (64^3 and 96 x 96 x 128 cells).  (1) FP64 iteration throughput
+    of the auto-tuned batch against the same problems iterated one by one;
+    (2) time to solve all of them to rel. residual tol with the batched
+    mixed-precision solver against plain FP64 solves one by one."""
+    wls = [300.0 + 800.0 * i / 3 for i in range(4)]
+    geoms = [(64, 64, 64, 10), (96, 96, 128, 11)]
+    probs = [inputs.solar_cell(nx, ny, nz, seed=sd, npml=6, wavelength_nm=wl,
+                               loss_range=(0.1, 0.5))
+             for nx, ny, nz, sd in geoms for wl in wls]
+    cells = sum(p.eps.size for p in probs)
+    out = {"problems": len(probs), "cells": cells, "wavelengths_nm": wls,
+           "grids": ["64x64x64", "96x96x128"], "tol": tol}
+    iters = 256
+    bt = thiim.Batch(probs, autotune=True)
+    out["batch_tuning"] = bt.tuning
+    bt.iterate(64)
+    bt.synchronize()
+    t = time.perf_counter()
+    bt.iterate(iters)
+    bt.synchronize()
+    out["batched_fp64_glups"] = cells * iters / (time.perf_counter() - t) / 1e9
+    bt.close()
+    tot = 0.0
+    for p in probs:
+        s = thiim.Solver(p, storage="compact")
+        s.iterate(8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.iterate(iters)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t
+        s.close()
+    out["one_by_one_fp64_glups"] = cells * iters / tot / 1e9
+    log(f"[bench] spectral: batched {out['batched_fp64_glups']:.2f} GLUP/s, one by one "
+        f"{out['one_by_one_fp64_glups']:.2f} GLUP/s")
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    bt = thiim.Batch(probs, precision="mixed", t_block=3)
+    rc, its, res = bt.solve(tol, 2000000, 0)
+    bt.synchronize()
+    dt_mixed = time.perf_counter() - t
+    bt.close()
+    out["batched_mixed"] = {"status": thiim.status_str(rc), "seconds": dt_mixed,
+                            "solves_per_s": len(probs) / dt_mixed,
+                            "max_rel_residual": float(res.max()), "sweeps": its.tolist()}
+    log(f"[bench] spectral: batched mixed solve {dt_mixed:.1f} s")
+    torch.cuda.empty_cache()
+    tot, its64, worst = 0.0, [], 0.0
+    for p in probs:
+        t = time.perf_counter()
+        s = thiim.Solver(p, storage="compact")
+        rc, it, r = s.solve(tol, 2000000, 500)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t
+        its64.append(it)
+        worst = max(worst, r)
+        s.close()
+        log(f"[bench] spectral: FP64 solve {len(its64)}/{len(probs)}: {it} iterations")
+    out["one_by_one_fp64"] = {"seconds": tot, "solves_per_s": len(probs) / tot,
+                              "max_rel_residual": worst, "iterations": its64}
+    out["speedup_solves_per_s"] = tot / dt_mixed
+    return out
+
+
 def traffic_for(kernel_name, n_cells):
     """Counter traffic (bytes per launch) if the committed summary matches
     the current kernel sources and grid, else None."""
@@ -217,6 +286,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the 1e-8 solve comparison")
     ap.add_argument("--solve-grid", default="128x128x256",
                     help="nx x ny x nz of the solve comparison")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="skip the batched spectral-sweep comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -292,6 +363,9 @@ def main():
     if not args.no_solve:
         nx_, ny_, nz_ = (int(v) for v in args.solve_grid.split("x"))
         solve = solve_context(torch, thiim, inputs, (nz_, ny_, nx_))
+    spectral = None
+    if not args.no_spectral:
+        spectral = spectral_context(torch, thiim, inputs)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -319,6 +393,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "solve_1e-8": solve,
+        "spectral_batch": spectral,
     }
     print(json.dumps(out), flush=True)
 

@@ -235,9 +235,27 @@ int thiim_batch_residual(thiim_batch *batch, double *rel_res);
 /* Iterates all contexts, checking every check_every iterations, and stops
  * advancing each one as soon as its residual is <= tol; iters[i] and
  * rel_res[i] (may be NULL) receive its iteration count and final residual.
- * THIIM_ENOTCONV if any context reached max_it first.  Synchronising. */
+ * THIIM_ENOTCONV if any context reached max_it first.  Synchronising.
+ * When every context was created with THIIM_PRECISION_MIXED, this runs the
+ * mixed-precision solver of thiim_solve for all of them at once: per step,
+ * each active problem's FP64 residual sweep, then the complex64 inner passes
+ * of all problems with the same T as one batched launch per pass (captured
+ * in a HIP graph per active set), each problem averaging its own window;
+ * check_every = inner sweeps per step (0: adaptive, driven by the slowest
+ * problem); iters[i] counts sweeps as thiim_solve does.  Contexts may not
+ * mix the two precisions. */
 int thiim_batch_solve(thiim_batch *batch, double tol, int max_it, int check_every,
                       int *iters, double *rel_res);
+
+/* Picks one sweep configuration for every context of the batch by timing
+ * the batched passes themselves (blocked regions 32x16, 64x8, 64x6 and fused
+ * tiles 64x8, 32x8, with each problem's automatic z chunk or a fixed one;
+ * trial passes from the current states into the spare buffers, so the
+ * states do not advance).  In a batch the launch is filled by all problems
+ * together, so the choice can differ from thiim_autotune's on each problem
+ * alone.  z_chunk = 0 in out means "each problem's automatic chunk".
+ * out may be NULL.  Synchronising. */
+int thiim_batch_autotune(thiim_batch *batch, int trial_iters, thiim_tuning *out);
 
 void thiim_batch_destroy(thiim_batch *batch);
 

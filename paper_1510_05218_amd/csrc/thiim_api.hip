@@ -826,7 +826,12 @@ namespace {
 
 constexpr int kGraphIters = 64;  // iterations per captured graph (a multiple of 4)
 
-size_t batch_bytes(int n) { return align_up((size_t)2 * n * sizeof(thiim::BatchItem), kAlign); }
+size_t batch_items_bytes(int n) {
+    return align_up((size_t)2 * n * sizeof(thiim::BatchItem), kAlign);
+}
+size_t batch_bytes(int n) {
+    return batch_items_bytes(n) + align_up((size_t)2 * n * sizeof(thiim::BatchItem32), kAlign);
+}
 
 void drop_graph(thiim_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -990,6 +995,181 @@ int batch_residual(thiim_batch* b, std::vector<double>& r) {
     return THIIM_OK;
 }
 
+// Mixed-precision batch solve: the defect-correction steps of solve_mixed
+// for all active problems at once -- per problem the FP64 residual sweep and
+// defect, then the complex64 inner passes of all problems with the same T as
+// one batched launch per pass (the inner phase of a step captured once in a
+// HIP graph per active set), each problem averaging its own last Kp passes
+// into x.  All problems run the same number of inner sweeps per step: m, or
+// with m = 0 the adaptive count of solve_mixed driven by the slowest problem.
+int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
+                      std::vector<int>& done, std::vector<double>& r, bool& diverged) {
+    const size_t n = b->ctx.size();
+    std::vector<int> Kp(n), T(n);
+    int m = 64;
+    for (size_t i = 0; i < n; ++i) {
+        thiim_ctx* c = b->ctx[i];
+        T[i] = c->inner_t;
+        Kp[i] = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau * T[i]));
+        if (Kp[i] < 1) Kp[i] = 1;
+        if (2 * Kp[i] * T[i] > m) m = 2 * Kp[i] * T[i];
+    }
+    if (m_user > 0) m = m_user;
+    std::vector<double> prev(n, INFINITY);
+    thiim::BatchItem32* base = (thiim::BatchItem32*)(b->ws + batch_items_bytes((int)n));
+    struct G32 {
+        int T;
+        std::vector<int> members;
+        int total;
+        thiim::BatchItem32* dev[2];
+    };
+    std::vector<G32> groups;
+    bool rebuild32 = true;
+    int graph_m = -1;
+    drop_graph(b);
+    for (;;) {
+        // FP64 residual sweep and defect of every active problem
+        std::vector<double> host(2 * n, 0.0);
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+            if (!b->active[i]) continue;
+            thiim_ctx* c = b->ctx[i];
+            e = one_pass(c, c->cur, 1 - c->cur);
+            if (e == hipSuccess)
+                e = thiim::launch_defect(c->F[c->cur], c->F[1 - c->cur], c->r32, c->cv.P, c->L.S,
+                                         c->L.N, (long long)c->g.nx * c->g.ny, c->part,
+                                         kResidBlocks, c->out, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&host[2 * i], c->out, 2 * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch mixed: residual");
+        bool any = false, weak = false;
+        for (size_t i = 0; i < n; ++i) {
+            if (!b->active[i]) continue;
+            thiim_ctx* c = b->ctx[i];
+            done[i] += 1;
+            r[i] = std::sqrt(host[2 * i]) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
+            if (!std::isfinite(r[i])) diverged = true;
+            if (!std::isfinite(r[i]) || r[i] <= tol || done[i] >= max_it) {
+                b->active[i] = 0;
+                rebuild32 = true;
+                continue;
+            }
+            any = true;
+            if (std::isfinite(prev[i]) && r[i] > kWeak * prev[i]) weak = true;
+        }
+        if (!any) break;
+        if (m_user <= 0 && weak && m < kMaxInner) m *= 2;
+        if (rebuild32) {
+            drop_graph(b);
+            groups.clear();
+            for (size_t i = 0; i < n; ++i) {
+                if (!b->active[i]) continue;
+                auto it = std::find_if(groups.begin(), groups.end(),
+                                       [&](const G32& gr) { return gr.T == T[i]; });
+                if (it == groups.end()) {
+                    groups.push_back(G32{T[i], {}, 0, {nullptr, nullptr}});
+                    it = groups.end() - 1;
+                }
+                it->members.push_back((int)i);
+            }
+            std::vector<thiim::BatchItem32> items;
+            for (auto& gr : groups) {
+                for (int par = 0; par < 2; ++par) {
+                    gr.dev[par] = base + items.size();
+                    int t = 0;
+                    for (int i : gr.members) {
+                        thiim_ctx* c = b->ctx[i];
+                        thiim::BatchItem32 it;
+                        it.ce = c->ce32;
+                        it.P32 = c->p32;
+                        it.r = c->r32;
+                        it.S = c->L.S;
+                        it.ph = make_float2((float)c->cv.K.ph.x, (float)c->cv.K.ph.y);
+                        it.phc = make_float2((float)c->cv.K.phc.x, (float)c->cv.K.phc.y);
+                        it.ph2 = make_float2((float)c->cv.K.ph2.x, (float)c->cv.K.ph2.y);
+                        it.ph2c = make_float2((float)c->cv.K.ph2c.x, (float)c->cv.K.ph2c.y);
+                        it.A = c->d32[par];
+                        it.B = c->d32[1 - par];
+                        it.g = c->geo;
+                        it.kchunk = c->inner_chunk;
+                        const int ox = c->inner_rx - 2 * gr.T, oy = c->inner_ry - 2 * gr.T;
+                        it.ntx = (c->g.nx + ox - 1) / ox;
+                        it.nty = (c->g.ny + oy - 1) / oy;
+                        it.ntz = (c->g.nz + it.kchunk - 1) / it.kchunk;
+                        it.tile_begin = t;
+                        t += it.ntx * it.nty * it.ntz;
+                        items.push_back(it);
+                    }
+                    gr.total = t;
+                }
+            }
+            e = hipMemcpyAsync(base, items.data(), items.size() * sizeof(thiim::BatchItem32),
+                               hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch mixed: item upload");
+            rebuild32 = false;
+        }
+        // complex64 inner phase (graph-captured when the stream allows)
+        auto inner = [&]() {
+            hipError_t err = hipSuccess;
+            for (auto& gr : groups) {
+                int P = 0;
+                for (int i : gr.members) {
+                    const int pi = std::max((m - 1 + gr.T - 1) / gr.T, Kp[i]);
+                    P = std::max(P, pi);
+                }
+                for (int i : gr.members)
+                    if (err == hipSuccess)
+                        err = thiim::launch_copy32(b->ctx[i]->r32, b->ctx[i]->d32[0],
+                                                   b->ctx[i]->L.S, b->ctx[i]->L.N, b->stream);
+                for (int p = 0; err == hipSuccess && p < P; ++p) {
+                    err = thiim::launch_inner32_batch(gr.dev[p & 1], (int)gr.members.size(),
+                                                      gr.total, gr.T, 32, 16, b->stream);
+                    for (int i : gr.members) {
+                        if (err != hipSuccess || p < P - Kp[i]) continue;
+                        thiim_ctx* c = b->ctx[i];
+                        err = thiim::launch_accum(c->F[c->cur], c->d32[(p + 1) & 1], 1.0 / Kp[i],
+                                                  c->L.S, c->L.N, b->stream);
+                    }
+                }
+            }
+            return err;
+        };
+        if (b->stream) {
+            if (!b->exec || graph_m != m) {
+                drop_graph(b);
+                e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return hip_fail(e, "batch mixed: begin capture");
+                hipError_t el = inner();
+                e = hipStreamEndCapture(b->stream, &b->graph);
+                if (el != hipSuccess) return hip_fail(el, "batch mixed: captured launch");
+                if (e != hipSuccess) return hip_fail(e, "batch mixed: end capture");
+                e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) return hip_fail(e, "batch mixed: instantiate");
+                graph_m = m;
+            }
+            e = hipGraphLaunch(b->exec, b->stream);
+        } else {
+            e = inner();
+        }
+        if (e != hipSuccess) return hip_fail(e, "batch mixed: inner passes");
+        for (auto& gr : groups) {
+            int P = 0;
+            for (int i : gr.members) P = std::max(P, std::max((m - 1 + gr.T - 1) / gr.T, Kp[i]));
+            for (int i : gr.members) {
+                done[i] += P * gr.T;
+                b->ctx[i]->iters += 1 + P * gr.T;
+                prev[i] = r[i];
+            }
+        }
+    }
+    drop_graph(b);
+    return THIIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1049,8 +1229,9 @@ int thiim_batch_residual(thiim_batch* b, double* rel_res) {
 int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, int* iters,
                       double* rel_res) {
     if (!b) return fail(THIIM_EINVAL, "batch is NULL");
-    if (!(tol > 0.0) || max_it < 0 || check_every < 1)
-        return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1");
+    const bool mixed0 = b->ctx[0]->g.precision == THIIM_PRECISION_MIXED;
+    if (!(tol > 0.0) || max_it < 0 || check_every < (mixed0 ? 0 : 1))
+        return fail(THIIM_EINVAL, "need tol > 0, max_it >= 0, check_every >= 1 (>= 0 MIXED)");
     const size_t n = b->ctx.size();
     std::fill(b->active.begin(), b->active.end(), 1);
     b->dirty = true;
@@ -1058,7 +1239,12 @@ int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, i
     std::vector<int> done(n, 0);
     int step_done = 0, rc = THIIM_OK;
     bool diverged = false;
-    for (;;) {
+    int mixed = 0;
+    for (size_t i = 0; i < n; ++i) mixed += b->ctx[i]->g.precision == THIIM_PRECISION_MIXED;
+    if (mixed && mixed != (int)n)
+        return fail(THIIM_EINVAL, "batch solve: contexts mix FP64 and MIXED precision");
+    if (mixed) rc = batch_solve_mixed(b, tol, max_it, check_every, done, r, diverged);
+    for (; !mixed;) {
         std::vector<double> now;
         rc = batch_residual(b, now);
         if (rc) break;
@@ -1091,6 +1277,88 @@ int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, i
     if (diverged) return fail(THIIM_EDIVERGED, "batch: a residual is not finite");
     for (size_t i = 0; i < n; ++i)
         if (!(r[i] <= tol)) return fail(THIIM_ENOTCONV, "batch: iteration limit reached");
+    return THIIM_OK;
+}
+
+int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
+    if (!b || trial_iters < 1) return fail(THIIM_EINVAL, "batch is NULL or trial_iters < 1");
+    struct Cfg {
+        int kernel, tx, ty, chunk;  // chunk 0: each problem's automatic chunk
+    };
+    std::vector<Cfg> cands;
+    const int regions[3][2] = {{32, 16}, {64, 8}, {64, 6}};
+    for (auto& r : regions)
+        for (int zc : {0, 32, 64}) cands.push_back({THIIM_KERNEL_BLOCKED, r[0], r[1], zc});
+    for (int zc : {0, 32}) {
+        cands.push_back({THIIM_KERNEL_FUSED, 64, 8, zc});
+        cands.push_back({THIIM_KERNEL_FUSED, 32, 8, zc});
+    }
+    auto apply_all = [&](const Cfg& k) {
+        for (thiim_ctx* c : b->ctx) {
+            const int ox = k.kernel == THIIM_KERNEL_BLOCKED ? k.tx - 4 : k.tx;
+            const int oy = k.kernel == THIIM_KERNEL_BLOCKED ? k.ty - 4 : k.ty;
+            const long long tiles = (long long)((c->g.nx + ox - 1) / ox) * ((c->g.ny + oy - 1) / oy);
+            int zc = k.chunk > 0 ? std::min(k.chunk, c->g.nz) : auto_chunk(c->g, tiles);
+            apply(c, Candidate{k.kernel, k.tx, k.ty, zc, 0.0});
+        }
+        b->dirty = true;
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(THIIM_EDEVICE, "batch autotune: event create");
+    int best = -1;
+    double best_ms = INFINITY;
+    int rc = THIIM_OK;
+    for (size_t i = 0; i < cands.size() && rc == THIIM_OK; ++i) {
+        apply_all(cands[i]);
+        rc = rebuild(b);
+        if (rc) break;
+        const int per = cands[i].kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
+        const int passes = (trial_iters + per - 1) / per;
+        // passes from the current states into the spare buffers (no advance)
+        auto launch_all = [&]() {
+            hipError_t e = hipSuccess;
+            for (auto& gr : b->groups) {
+                if (e != hipSuccess) break;
+                e = gr.blocked ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                             gr.total, 2, gr.tx, gr.ty, b->stream)
+                               : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                           gr.total, gr.tx, gr.ty, b->stream);
+            }
+            return e;
+        };
+        hipError_t e = launch_all();
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int p = 0; e == hipSuccess && p < passes; ++p) e = launch_all();
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "batch autotune trial");
+            break;
+        }
+        const double per_it = ms / (passes * per);
+        if (per_it < best_ms) {
+            best_ms = per_it;
+            best = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    apply_all(cands[best]);
+    if (out) {
+        out->kernel = cands[best].kernel;
+        out->tile_x = cands[best].tx;
+        out->tile_y = cands[best].ty;
+        out->t_block = cands[best].kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
+        out->z_chunk = cands[best].chunk;
+        out->ms_per_iteration = best_ms;
+        out->model_ms = 0.0;
+        out->candidates = (int)cands.size();
+        out->timed = (int)cands.size();
+    }
     return THIIM_OK;
 }
 

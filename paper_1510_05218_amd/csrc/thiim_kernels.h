@@ -60,6 +60,22 @@ struct BatchItem {
     int ntx, nty, ntz;
 };
 
+// One problem of a batched complex64 inner pass (mixed precision): the
+// inner-sweep coefficient data, residual r, d buffers, grid and tile range.
+struct BatchItem32 {
+    const float4* ce;
+    const PlaneCoef32* P32;
+    const float2* r;
+    long long S;
+    float2 ph, phc, ph2, ph2c;
+    const float2* A;
+    float2* B;
+    Geo g;
+    int kchunk;
+    int tile_begin;
+    int ntx, nty, ntz;
+};
+
 struct BuildArgs {
     const double2* eps_in;   // (eps', eps'') per cell
     const double* sig_e;     // nz, device
@@ -102,6 +118,8 @@ hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long 
 hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
                               int tile_y, hipStream_t s);
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
+                                int ry, hipStream_t s);
+hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
                                 int ry, hipStream_t s);
 // ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all
 // six, 3: E only) into out[0], out[1].

@@ -1128,8 +1128,8 @@ __global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* 
 // problem, sharing its L2).  A workgroup finds its item by binary search over
 // the items' first-tile indices (uniform, scalar loads).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int batch_find(const BatchItem* __restrict__ items, int nitems,
-                                          int t) {
+template <class Item>
+__device__ __forceinline__ int batch_find(const Item* __restrict__ items, int nitems, int t) {
     int lo = 0, hi = nitems - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1139,7 +1139,8 @@ __device__ __forceinline__ int batch_find(const BatchItem* __restrict__ items, i
     return lo;
 }
 
-__device__ __forceinline__ Tile batch_tile(const BatchItem& it, int t) {
+template <class Item>
+__device__ __forceinline__ Tile batch_tile(const Item& it, int t) {
     const int local = t - it.tile_begin;
     Tile TT;
     TT.bx = local % it.ntx;
@@ -1155,6 +1156,24 @@ __global__ __launch_bounds__(TX* TY) void k_fused_batch(const BatchItem* __restr
     const int i = batch_find(items, nitems, G.bx);
     const BatchItem& it = items[i];
     fused_body<TX, TY>(compact_view(it.cv), it.A, it.B, it.g, it.kchunk, batch_tile(it, G.bx));
+}
+
+template <int RX, int RY, int T>
+__global__ __launch_bounds__(RX* RY) void k_inner32_batch(const BatchItem32* __restrict__ items,
+                                                          int nitems, int total) {
+    const Tile G = tile_of(total, 1, 1);
+    const int i = batch_find(items, nitems, G.bx);
+    const BatchItem32& it = items[i];
+    Pol32 pol;
+    pol.ce = it.ce;
+    pol.P32 = it.P32;
+    pol.r = it.r;
+    pol.S = it.S;
+    pol.ph = it.ph;
+    pol.phc = it.phc;
+    pol.ph2 = it.ph2;
+    pol.ph2c = it.ph2c;
+    blocked_body<RX, RY, T>(pol, it.A, it.B, it.g, it.kchunk, batch_tile(it, G.bx));
 }
 
 template <int RX, int RY, int T>
@@ -1773,6 +1792,20 @@ hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, i
                            nitems, total);
     else if (rx == 32 && ry == 16)
         hipLaunchKernelGGL((k_blocked_batch<32, 16, 2>), dim3(total), dim3(512), 0, s, items,
+                           nitems, total);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
+                                int ry, hipStream_t s) {
+    if (nitems < 1 || total < 1 || rx != 32 || ry != 16) return hipErrorInvalidValue;
+    if (T == 2)
+        hipLaunchKernelGGL((k_inner32_batch<32, 16, 2>), dim3(total), dim3(512), 0, s, items,
+                           nitems, total);
+    else if (T == 3)
+        hipLaunchKernelGGL((k_inner32_batch<32, 16, 3>), dim3(total), dim3(512), 0, s, items,
                            nitems, total);
     else
         return hipErrorInvalidValue;

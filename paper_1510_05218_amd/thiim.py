@@ -33,7 +33,8 @@ SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_set_fields", "thiim_get_coeffs", "thiim_iterations",
            "thiim_adjoint_grad", "thiim_autotune", "thiim_batch_workspace_bytes",
            "thiim_batch_create", "thiim_batch_iterate", "thiim_batch_residual",
-           "thiim_batch_solve", "thiim_batch_destroy", "thiim_destroy",
+           "thiim_batch_solve", "thiim_batch_autotune", "thiim_batch_destroy",
+           "thiim_destroy",
            "thiim_last_error", "thiim_status_str")
 
 
@@ -101,6 +102,7 @@ def lib():
         L.thiim_batch_iterate.argtypes = [vp, i]
         L.thiim_batch_residual.argtypes = [vp, P(d)]
         L.thiim_batch_solve.argtypes = [vp, d, i, i, P(i), P(d)]
+        L.thiim_batch_autotune.argtypes = [vp, i, P(Tuning)]
         L.thiim_batch_destroy.argtypes = [vp]
         L.thiim_batch_destroy.restype = None
         L.thiim_destroy.argtypes = [vp]
@@ -231,6 +233,12 @@ def thiim_batch_solve(batch, n: int, tol: float, max_it: int, check_every: int =
     if rc not in (THIIM_OK, THIIM_ENOTCONV):
         _check(rc)
     return rc, np.array(it[:]), np.array(r[:])
+
+
+def thiim_batch_autotune(batch, trial_iters: int = 8) -> Tuning:
+    out = Tuning()
+    _check(lib().thiim_batch_autotune(batch, int(trial_iters), ctypes.byref(out)))
+    return out
 
 
 def thiim_batch_destroy(batch):
@@ -375,10 +383,10 @@ class Solver:
 class Batch:
     """Many problems advanced together (thiim_batch_*): ``problems`` is a list
     of ``inputs.Problem``; each gets a compact-storage :class:`Solver` on one
-    shared non-default stream (so that the batch can capture HIP graphs),
-    optionally auto-tuned."""
+    shared non-default stream (so that the batch can capture HIP graphs);
+    ``autotune`` picks the batch's sweep configuration (thiim_batch_autotune)."""
 
-    def __init__(self, problems, autotune=False, trial_iters=6, device="cuda", stream=None,
+    def __init__(self, problems, autotune=False, trial_iters=8, device="cuda", stream=None,
                  **solver_kw):
         import torch
 
@@ -386,12 +394,13 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.solvers = [Solver(p, storage="compact", device=device, stream=self.stream,
                                **solver_kw) for p in problems]
-        self.tuning = [s.autotune(trial_iters) if autotune else None for s in self.solvers]
         self.n = len(self.solvers)
         self.ws_bytes = thiim_batch_workspace_bytes(self.n)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.batch = thiim_batch_create([s.ctx for s in self.solvers],
                                         self.workspace.data_ptr(), self.ws_bytes)
+        self.tuning = (thiim_batch_autotune(self.batch, trial_iters).as_dict() if autotune
+                       else None)
 
     def iterate(self, n):
         thiim_batch_iterate(self.batch, n)
