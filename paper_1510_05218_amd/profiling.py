@@ -8,9 +8,14 @@
   ``bench.py --calib-copy``).  The result records a hash of the kernel
   sources; ``bench.py`` reports the traffic only while that hash matches.
 
+* ``run_mixed``: a GPU workload for profiling the complex64 inner sweeps --
+  two defect-correction steps of the mixed-precision solver on the n^3
+  benchmark problem, with T = 2 and with T = 3 inner passes.
+
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
+    python -m paper_1510_05218_amd.profiling run_mixed [n]
 """
 from __future__ import annotations
 
@@ -127,6 +132,30 @@ def kernel_stats_md(stats_csv, n_cells, out_md, command):
         f.write("\n".join(lines) + "\n")
 
 
+def run_mixed(n=512):
+    """Two correction steps (FP64 residual sweep + 40 / 60 inner sweeps) of
+    the mixed solver with T = 2 and T = 3 inner passes on the n^3 problem."""
+    import time
+
+    import torch
+
+    from . import inputs, thiim
+
+    pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200 if n >= 128 else 0)
+    dev = inputs.Problem(**{**pb.__dict__})
+    dev.eps = torch.from_numpy(pb.eps).cuda()
+    dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
+    for T, m in ((2, 41), (3, 61)):
+        s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=T)
+        torch.cuda.synchronize()
+        t = time.time()
+        rc, it, r = s.solve(1e-30, 2, m)
+        torch.cuda.synchronize()
+        print(json.dumps({"T": T, "sweeps": it, "s": round(time.time() - t, 3)}), flush=True)
+        s.close()
+        torch.cuda.empty_cache()
+
+
 def main(argv):
     if argv[0] == "traffic":
         fetch, write, n, out, cmd = argv[1:6]
@@ -135,6 +164,8 @@ def main(argv):
         stats, n, out, cmd = argv[1:5]
         kernel_stats_md(stats, int(n), out, cmd)
         print(open(out).read())
+    elif argv[0] == "run_mixed":
+        run_mixed(int(argv[1]) if len(argv) > 1 else 512)
     else:
         raise SystemExit(__doc__)
 
