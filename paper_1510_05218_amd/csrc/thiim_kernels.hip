@@ -353,9 +353,15 @@ struct CompactCoefs {
     }
     __device__ __forceinline__ void e(int k, long long po, uint32_t bo, double2 t[6],
                                       double2 c[6], double2& sa, double2& sb) const {
+        e_from(k, ldo(eps + po, bo), po, bo, t, c, sa, sb);
+    }
+    // the same from an eps value already loaded
+    __device__ __forceinline__ void e_from(int k, double2 eps_k, long long po, uint32_t bo,
+                                           double2 t[6], double2 c[6], double2& sa,
+                                           double2& sb) const {
         const double sig_e = P[k].sig_e;
         const int has_src = P[k].has_src;
-        const ECoef r = cell_e(ldo(eps + po, bo), sig_e, K);
+        const ECoef r = cell_e(eps_k, sig_e, K);
         t[0] = r.t1; c[0] = r.c1;
         t[1] = r.t0; c[1] = r.c0;
         t[2] = r.t1; c[2] = r.c1;
@@ -388,9 +394,28 @@ struct Pol64 {
     static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
     static constexpr bool H_SRC_AFTER = false;
     static constexpr bool CARRY = false;
-    static constexpr bool PREFETCH = false;  // measured: no gain at 250 VGPRs
-    using CRec = double2;  // unused (no carried coefficient record)
+    // compact storage: eps of each E plane is read at the top of the step and
+    // handed to the next stage in registers (one read per cell and pass, in
+    // flight together with the field reads)
+    static constexpr bool CARRY_REC = CP::COMPACT;
+    using CRec = double2;
     CP cp;
+    __device__ __forceinline__ CRec load_crec(long long po, uint32_t bo) const {
+        if constexpr (CP::COMPACT) return ldo(cp.eps + po, bo);
+        else return CRec{};
+    }
+    __device__ __forceinline__ void ecoef_rec(int k, CRec eps_k, long long po, uint32_t bo,
+                                              V t[6], V c[6], V src[6]) const {
+        if constexpr (CP::COMPACT) {
+            double2 sa, sb;
+            cp.e_from(k, eps_k, po, bo, t, c, sa, sb);
+            src[0] = sa;
+            src[2] = sb;
+            src[1] = src[3] = src[4] = src[5] = czero();
+        } else {
+            ecoef(k, po, bo, t, c, src);
+        }
+    }
     __device__ __forceinline__ void hcoef(int k, long long po, uint32_t bo, V t[6], V c[6],
                                           V src[6]) const {
         double2 sa, sb;
@@ -427,7 +452,7 @@ struct Pol32 {
     // stage, and handed down the stage pipeline in registers (each later
     // stage works one plane lower)
     static constexpr bool CARRY = true;
-    static constexpr bool PREFETCH = true;
+    static constexpr bool CARRY_REC = true;
     const float4* __restrict__ ce;       // per-cell record (k_prep32)
     const PlaneCoef32* __restrict__ P32;  // per-plane H coefficients
     const float2* __restrict__ r;        // 12 arrays, stride S
@@ -930,66 +955,30 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
         }
     }
     if (ks > 0 && valid) load6v(AE, S, (ks - 1) * plane, bo, e0p);
-    // PF: the HBM reads of plane k (E_0 and H_0 parts; with CARRY also the
-    // sources and the coefficient record) are issued one step ahead, so that
-    // they are in flight while the stages of the previous plane run.  It
-    // costs ~48 VGPRs and is taken where the carried state leaves room and a
-    // gain was measured.
-    constexpr bool PF = P::PREFETCH && T == 2;
-    V e0n[6], h0n[6];
-    V rHn[6], rEn[6];
-    typename P::CRec crn = {};
-    auto prefetch = [&](int kk) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) e0n[q] = h0n[q] = vzero<V>();
-        if (valid && kk < g.nz) {
-            load6v(AE, S, kk * plane, bo, e0n);
-            load6v(A, S, kk * plane, bo, h0n);
-        }
-        if constexpr (P::CARRY) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) rHn[q] = rEn[q] = vzero<V>();
-            if (valid && kk < g.nz) pol.load_h_src(kk * plane, bo, rHn);
-            if (valid && kk >= 1 && kk - 1 < g.nz) {
-                pol.load_e_src((kk - 1) * plane, bo, rEn);
-                crn = pol.load_crec((kk - 1) * plane, bo);
-            }
-        }
-    };
-    if constexpr (PF) prefetch(ks);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
         const int par = k & 1;
-        // ---- E_0(k) sums into LDS
+        // every HBM read of the step is issued here, before the first barrier,
+        // so that their latencies overlap: E_0 and H_0 of plane k, and the
+        // sources or coefficient record that the policy carries
         V e0c[6], h0c[6];
-        if constexpr (PF) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                e0c[q] = e0n[q];
-                h0c[q] = h0n[q];
-            }
-            if constexpr (P::CARRY) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    rHq[0][q] = rHn[q];
-                    rEq[0][q] = rEn[q];
-                }
-                crq[0] = crn;
-            }
-            if (k < kend) prefetch(k + 1);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) e0c[q] = vzero<V>();
-            if (k < g.nz && valid) load6v(AE, S, k * plane, bo, e0c);
-            if constexpr (P::CARRY) {
-                if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
-                if (valid && k >= 1 && k - 1 < g.nz) {
-                    pol.load_e_src((k - 1) * plane, bo, rEq[0]);
-                    crq[0] = pol.load_crec((k - 1) * plane, bo);
-                }
-            }
+        for (int q = 0; q < 6; ++q) e0c[q] = h0c[q] = vzero<V>();
+        if (k < g.nz && valid) {
+            load6v(AE, S, k * plane, bo, e0c);
+            load6v(A, S, k * plane, bo, h0c);
         }
+        if constexpr (P::CARRY) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) rHq[0][q] = rEq[0][q] = vzero<V>();
+            if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
+            if (valid && k >= 1 && k - 1 < g.nz) pol.load_e_src((k - 1) * plane, bo, rEq[0]);
+        }
+        if constexpr (P::CARRY_REC) {
+            if (valid && k >= 1 && k - 1 < g.nz) crq[0] = pol.load_crec((k - 1) * plane, bo);
+        }
+        // ---- E_0(k) sums into LDS
         LE[0][0][me] = cadd(e0c[0], e0c[1]);
         LE[0][1][me] = cadd(e0c[2], e0c[3]);
         LE[0][2][me] = cadd(e0c[4], e0c[5]);
@@ -1007,12 +996,8 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 const long long po = kh * plane;
                 // old value: H_{s-1}(kh)
                 if (s == 1) {
-                    if constexpr (PF) {
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) h[q] = h0c[q];
-                    } else {
-                        load6v(A, S, po, bo, h);
-                    }
+                    for (int q = 0; q < 6; ++q) h[q] = h0c[q];
                 } else {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];
@@ -1089,6 +1074,8 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                     pol.ecoef_c(ke, crq[s - 1], t, c);
 #pragma unroll
                     for (int q = 0; q < 6; ++q) src[q] = rEq[s - 1][q];
+                } else if constexpr (P::CARRY_REC) {
+                    pol.ecoef_rec(ke, crq[s - 1], po, bo, t, c, src);
                 } else {
                     pol.ecoef(ke, po, bo, t, c, src);
                 }
@@ -1121,10 +1108,13 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 if (P::H_SRC_AFTER && q < 3) hcs[s][q] = hns[s - 1][q];
             }
         }
+        if constexpr (P::CARRY_REC) {
+#pragma unroll
+            for (int s = T - 1; s >= 1; --s) crq[s] = crq[s - 1];
+        }
         if constexpr (P::CARRY) {
 #pragma unroll
             for (int s = T - 1; s >= 1; --s) {
-                crq[s] = crq[s - 1];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
                     rHq[s][q] = rHq[s - 1][q];
