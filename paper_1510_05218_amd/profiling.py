@@ -13,7 +13,7 @@
   benchmark problem, with T = 2 and with T = 3 inner passes.
 
 Usage:
-    python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD
+    python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
     python -m paper_1510_05218_amd.profiling run_mixed [n]
 """
@@ -87,10 +87,15 @@ def _calibration(agg, expected):
     raise RuntimeError("calibration copy not found in the counter file")
 
 
-def traffic_summary(fetch_csv, write_csv, n_cells, out_json, command):
+def traffic_summary(fetch_csv, write_csv, n_cells, out_json, command, scales=None):
+    """scales = (fetch, write) counter factors measured in another run of the
+    same part, for runs without a calibration copy."""
     fetch, write = _per_kernel(fetch_csv), _per_kernel(write_csv)
-    f_scale = _calibration(fetch, CALIB_BYTES)
-    w_scale = _calibration(write, CALIB_BYTES)
+    if scales is None:
+        f_scale = _calibration(fetch, CALIB_BYTES)
+        w_scale = _calibration(write, CALIB_BYTES)
+    else:
+        f_scale, w_scale = scales
     kernels = {}
     for name in sorted(set(fetch) & set(write)):
         if not name.startswith("k_"):
@@ -159,7 +164,8 @@ def run_mixed(n=512):
 def main(argv):
     if argv[0] == "traffic":
         fetch, write, n, out, cmd = argv[1:6]
-        print(json.dumps(traffic_summary(fetch, write, int(n), out, cmd), indent=1))
+        scales = (float(argv[6]), float(argv[7])) if len(argv) > 7 else None
+        print(json.dumps(traffic_summary(fetch, write, int(n), out, cmd, scales), indent=1))
     elif argv[0] == "stats":
         stats, n, out, cmd = argv[1:5]
         kernel_stats_md(stats, int(n), out, cmd)
