@@ -98,7 +98,7 @@ typedef struct {
     int z_chunk;      /* z planes per workgroup stream (0 = auto) */
     int storage;      /* THIIM_STORAGE_FULL or THIIM_STORAGE_COMPACT */
     int precision;    /* THIIM_PRECISION_FP64 or THIIM_PRECISION_MIXED */
-    int adjoint;      /* 1: reserve the buffers of thiim_adjoint_grad (27 more
+    int adjoint;      /* 1: reserve the buffers of thiim_adjoint_grad (51 more
                        * arrays; needs THIIM_STORAGE_COMPACT), else 0 */
     void *stream;     /* hipStream_t */
 } thiim_grid;
@@ -173,12 +173,19 @@ int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
  * only coefficients that depend on eps; the PML profiles are held fixed).
  * The current state should be converged (thiim_solve); it is not changed.
  *   weight    device, N doubles: w_p
- *   tol > 0   iterate until ||P(lam_n - lam_{n-1})_E|| / ||P g_E|| <= tol,
- *             checked every check_every iterations, or max_it iterations
+ *   tol > 0   solve to ||P(M^T lam + g - lam)_E|| / ||P g_E|| <= tol by
+ *             defect correction: r = M^T lam + g - lam, then m sweeps
+ *             d <- M^T d + r (m = max(check_every, 2 Kp), doubled while a
+ *             step gains less than 0.3) and lam += the mean of d over the last
+ *             Kp = round(2 pi / (omega tau)) sweeps (one rotation period of the
+ *             modes an iteration rotates by e^{-i omega tau}; the plain
+ *             transposed iteration converges much more slowly where the PML
+ *             conductivity is small), until tol or max_it sweeps
  *             (THIIM_ENOTCONV; the outputs are still written)
- *   tol <= 0  exactly max_it iterations (check_every unused)
+ *   tol <= 0  exactly max_it plain transposed iterations lam <- M^T lam + g
+ *             from lam = 0 (check_every unused)
  *   grad_eps  device, 2*N doubles: (dJ/deps', dJ/deps'') per cell
- *   J, iters, rel_res  host, may be NULL
+ *   J, iters (transposed sweeps run), rel_res  host, may be NULL
  * Needs a context created with grid.adjoint = 1 (compact storage); the
  * transposed sweep uses the fused tile and z chunk.  Synchronising. */
 int thiim_adjoint_grad(thiim_ctx *ctx, const double *weight, double tol, int max_it,

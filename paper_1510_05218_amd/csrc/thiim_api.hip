@@ -42,7 +42,7 @@ struct Layout {
     size_t off_a, off_b;
     size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
     size_t off_ce, off_p32;   // mixed precision: per-cell float4 records, nz plane rows
-    size_t off_lam, off_g;    // adjoint: 2 x 12 + 3 complex128 arrays
+    size_t off_lam, off_g;    // adjoint: 4 x 12 + 3 complex128 arrays
     size_t total;
 };
 
@@ -77,7 +77,7 @@ Layout layout_of(const thiim_grid* g) {
     L.off_lam = L.off_g = 0;
     if (g->adjoint) {
         L.off_lam = off;
-        off += (size_t)24 * L.S * 16;
+        off += (size_t)48 * L.S * 16;
         L.off_g = off;
         off += (size_t)3 * L.S * 16;
     }
@@ -158,7 +158,7 @@ struct thiim_ctx {
     float4* ce32;                 // per-cell complex64 E-coefficient records
     thiim::PlaneCoef32* p32;      // per-plane complex64 H coefficients
     int inner_t, inner_rx, inner_ry, inner_chunk;
-    double2* lam[2];  // adjoint buffers
+    double2* lam[4];  // adjoint buffers
     double2* gadj;    // adjoint source, 3 arrays
 };
 
@@ -303,7 +303,7 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->ce32 = L.off_ce ? (float4*)(c->ws + L.off_ce) : nullptr;
     c->p32 = L.off_p32 ? (thiim::PlaneCoef32*)(c->ws + L.off_p32) : nullptr;
     c->lam[0] = L.off_lam ? (double2*)(c->ws + L.off_lam) : nullptr;
-    c->lam[1] = L.off_lam ? c->lam[0] + 12 * L.S : nullptr;
+    for (int i = 1; i < 4; ++i) c->lam[i] = L.off_lam ? c->lam[0] + 12 * i * L.S : nullptr;
     c->gadj = L.off_g ? (double2*)(c->ws + L.off_g) : nullptr;
     c->cur = 0;
     c->iters = 0;
@@ -563,47 +563,76 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
     const double jval = host[0];
     e = thiim::launch_fill_zero(c->lam[0], 24 * S, c->stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint: zero");
-    int li = 0, done = 0;
+    int li = 0, done = 0, rc = THIIM_OK;
     double r = 0.0, norm0 = 0.0;
-    auto sweep = [&]() {
-        hipError_t err = thiim::launch_adjoint(c->cv, c->lam[li], c->lam[1 - li], c->gadj,
-                                               c->geo, c->tile_x, c->tile_y, c->z_chunk,
-                                               c->stream);
-        li = 1 - li;
-        ++done;
-        return err;
+    auto sweep = [&](int src, int dst, const double2* G, bool dense) {
+        return thiim::launch_adjoint(c->cv, c->lam[src], c->lam[dst], G, dense, c->geo,
+                                     c->tile_x, c->tile_y, c->z_chunk, c->stream);
     };
-    // ||P lam_E||, P the split-pair sum, of the last two iterates
-    auto measure = [&](double* rr) {
+    // ||P(lam_b - lam_a)_E|| / ||P g_E|| (P: split-pair sum, R19)
+    auto measure = [&](int a, int b, double* rr) {
         double r2 = 0, b2 = 0;
-        int rc = reduce_pair(c, c->lam[1 - li], c->lam[li], 3, &r2, &b2);
-        if (rc) return rc;
-        if (done == 1) norm0 = std::sqrt(b2);  // lam_1 = g
+        int rc2 = reduce_pair(c, c->lam[a], c->lam[b], 3, &r2, &b2);
+        if (rc2) return rc2;
+        if (norm0 == 0.0) norm0 = std::sqrt(b2);  // first call: lam_a = 0, lam_b = g
         *rr = norm0 > 0 ? std::sqrt(r2) / norm0 : 0.0;
         return THIIM_OK;
     };
-    int rc = THIIM_OK;
-    if (max_it > 0) {
-        e = sweep();
-        if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
-        rc = measure(&r);
-        if (rc) return rc;
-        r = norm0 > 0 ? 1.0 : 0.0;
-    }
-    while (done < max_it && !(tol > 0.0 && r <= tol)) {
-        const int step = tol > 0.0 ? (check_every < max_it - done ? check_every : max_it - done)
-                                   : max_it - done;
-        for (int s = 0; s < step; ++s) {
-            e = sweep();
+    if (!(tol > 0.0)) {
+        // exactly max_it transposed iterations from lam = 0
+        for (int it = 0; it < max_it; ++it) {
+            e = sweep(li, 1 - li, c->gadj, false);
             if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
+            li = 1 - li;
+            ++done;
+            if (it == 0) {
+                rc = measure(1 - li, li, &r);
+                if (rc) return rc;
+            }
         }
-        rc = measure(&r);
-        if (rc) return rc;
-        if (!std::isfinite(r)) {
-            if (iters) *iters = done;
-            if (rel_res) *rel_res = r;
-            return fail(THIIM_EDIVERGED, "adjoint residual is not finite");
+        if (max_it > 1) {
+            rc = measure(1 - li, li, &r);
+            if (rc) return rc;
         }
+    } else {
+        // Defect correction with period-averaged corrections (as in the
+        // mixed-precision solver, in FP64): r = M^T lam + g - lam, then
+        // d <- M^T d + r and lam += the mean of d over the last Kp sweeps, one
+        // rotation period of the modes an iteration rotates by e^{-iw tau}.
+        // Compared with the plain transposed iteration this removes their
+        // rotating part and damps the slowly decaying modes of the first PML
+        // planes, where sigma is small.  Buffers: lam = 0, Phi = 1, d = 2, 3.
+        int Kp = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau));
+        if (Kp < 1) Kp = 1;
+        int m = check_every > 2 * Kp ? check_every : 2 * Kp;
+        double prev = INFINITY;
+        for (;;) {
+            e = sweep(0, 1, c->gadj, false);
+            if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
+            ++done;
+            rc = measure(0, 1, &r);
+            if (rc) return rc;
+            if (!std::isfinite(r)) {
+                if (iters) *iters = done;
+                if (rel_res) *rel_res = r;
+                return fail(THIIM_EDIVERGED, "adjoint residual is not finite");
+            }
+            if (r <= tol || done >= max_it) break;
+            if (std::isfinite(prev) && r > 0.3 * prev && m < (1 << 15)) m *= 2;
+            prev = r;
+            e = thiim::launch_sub(c->lam[0], c->lam[1], S, N, c->stream);  // r
+            if (e == hipSuccess) e = thiim::launch_copy(c->lam[1], c->lam[2], 12 * S, c->stream);
+            int di = 2;
+            for (int p = 0; e == hipSuccess && p < m; ++p) {
+                e = sweep(di, 5 - di, c->lam[1], true);
+                di = 5 - di;
+                if (e == hipSuccess && p >= m - Kp)
+                    e = thiim::launch_axpy(c->lam[0], c->lam[di], 1.0 / Kp, S, N, c->stream);
+            }
+            if (e != hipSuccess) return hip_fail(e, "adjoint: correction");
+            done += m;
+        }
+        li = 0;
     }
     e = thiim::launch_adj_grad(c->cv, c->F[c->cur], c->F[other], c->lam[li], weight, c->geo,
                                (double2*)grad_eps, c->stream);

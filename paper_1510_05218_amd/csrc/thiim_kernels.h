@@ -129,7 +129,12 @@ hipError_t launch_resid(const double2* A, const double2* B, long long S, long lo
 // (3 arrays); the objective / adjoint source of the state X (J in out[0]);
 // the gradient (dJ/deps', dJ/deps'') per cell.
 hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
-                          const Geo& g, int tile_x, int tile_y, int kchunk, hipStream_t s);
+                          bool dense, const Geo& g, int tile_x, int tile_y, int kchunk,
+                          hipStream_t s);
+// 12-array FP64 helpers: Y -= X; X += w D.
+hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s);
+hipError_t launch_axpy(double2* X, const double2* D, double w, long long S, long long N,
+                       hipStream_t s);
 hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
                              long long N, double2* G, double* part, int nblk, double* out,
                              hipStream_t s);

@@ -1290,7 +1290,10 @@ __global__ __launch_bounds__(256) void k_resid_final(const double* __restrict__ 
 // k_adjoint has the structure of k_fused: tile + halo ring through LDS, z
 // streamed, step 2 one plane behind step 1.
 // ---------------------------------------------------------------------------
-template <int TX, int TY, class CP>
+// DENSE = false: G holds g_a (3 arrays), added to both parts of E_a;
+// DENSE = true:  G holds a source for every part (12 arrays), added to each
+//                part after its transposed update (lam <- M^T lam + G).
+template <int TX, int TY, class CP, bool DENSE>
 __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __restrict__ A,
                                                     double2* __restrict__ B,
                                                     const double2* __restrict__ G, Geo g,
@@ -1421,7 +1424,13 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
                     v[q] = cmul(c[q], lh);
                     l[q] = cmul(t[q], lh);
                 }
-                if (own_store && k < k1) store6(B, S, po, bo, l);
+                if (own_store && k < k1) {
+                    if constexpr (DENSE) {
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) l[q] = cadd(l[q], ldo(G + q * S + po, bo));
+                    }
+                    store6(B, S, po, bo, l);
+                }
             }
             if (has_hh && halo_valid) {
                 const double2 inc[3] = {
@@ -1444,11 +1453,17 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
                 csub(csub(vp[4], Vs[2][ho + HW]), csub(vp[2], v[2])),
                 csub(csub(vp[0], v[0]), csub(vp[5], Vs[3][ho + 1])),
                 csub(csub(vp[3], Vs[1][ho + 1]), csub(vp[1], Vs[0][ho + HW]))};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) inc[a] = cadd(inc[a], ldo(G + a * S + pm, bo));
             double2 out[6];
+            if constexpr (DENSE) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) out[q] = cadd(ep[q], inc[q / 2]);
+                for (int q = 0; q < 6; ++q)
+                    out[q] = cadd(cadd(ep[q], inc[q / 2]), ldo(G + (6 + q) * S + pm, bo));
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) inc[a] = cadd(inc[a], ldo(G + a * S + pm, bo));
+#pragma unroll
+                for (int q = 0; q < 6; ++q) out[q] = cadd(ep[q], inc[q / 2]);
+            }
             if (own_store) store6(BE, S, pm, bo, out);
         }
         __syncthreads();
@@ -1675,6 +1690,29 @@ __global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, d
     }
 }
 
+// Y -= X over 12 arrays (FP64)
+__global__ void k_sub(const double2* __restrict__ X, double2* __restrict__ Y, long long S,
+                      long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) Y[q * S + p] = csub(Y[q * S + p], X[q * S + p]);
+    }
+}
+
+// X += w D over 12 arrays (FP64)
+__global__ void k_axpy(double2* __restrict__ X, const double2* __restrict__ D, double w,
+                       long long S, long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double2 x = X[q * S + p], d = D[q * S + p];
+            X[q * S + p] = make_double2(__fma_rn(w, d.x, x.x), __fma_rn(w, d.y, x.y));
+        }
+    }
+}
+
 // complex64 copy of 12 arrays (d = r starts the inner iteration)
 __global__ void k_copy32(const float2* __restrict__ src, float2* __restrict__ dst, long long S,
                          long long N) {
@@ -1823,27 +1861,36 @@ hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total,
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
-                          const Geo& g, int tile_x, int tile_y, int kchunk, hipStream_t s) {
-    if (!cv.compact) return hipErrorInvalidValue;
-    const CompactCoefs cp = compact_of(cv);
+template <bool DENSE>
+static hipError_t adjoint_impl(const CompactCoefs& cp, const double2* A, double2* B,
+                               const double2* G, const Geo& g, int tile_x, int tile_y,
+                               int kchunk, hipStream_t s) {
     dim3 grid(((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y) *
               nchunks(g, kchunk));
     if (tile_x == 64 && tile_y == 8)
-        hipLaunchKernelGGL((k_adjoint<64, 8, CompactCoefs>), grid, dim3(512), 0, s, cp, A, B, G,
-                           g, kchunk);
+        hipLaunchKernelGGL((k_adjoint<64, 8, CompactCoefs, DENSE>), grid, dim3(512), 0, s, cp, A,
+                           B, G, g, kchunk);
     else if (tile_x == 32 && tile_y == 8)
-        hipLaunchKernelGGL((k_adjoint<32, 8, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B, G,
-                           g, kchunk);
+        hipLaunchKernelGGL((k_adjoint<32, 8, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp, A,
+                           B, G, g, kchunk);
     else if (tile_x == 64 && tile_y == 4)
-        hipLaunchKernelGGL((k_adjoint<64, 4, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B, G,
-                           g, kchunk);
+        hipLaunchKernelGGL((k_adjoint<64, 4, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp, A,
+                           B, G, g, kchunk);
     else if (tile_x == 16 && tile_y == 16)
-        hipLaunchKernelGGL((k_adjoint<16, 16, CompactCoefs>), grid, dim3(256), 0, s, cp, A, B,
-                           G, g, kchunk);
+        hipLaunchKernelGGL((k_adjoint<16, 16, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp,
+                           A, B, G, g, kchunk);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
+                          bool dense, const Geo& g, int tile_x, int tile_y, int kchunk,
+                          hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    const CompactCoefs cp = compact_of(cv);
+    return dense ? adjoint_impl<true>(cp, A, B, G, g, tile_x, tile_y, kchunk, s)
+                 : adjoint_impl<false>(cp, A, B, G, g, tile_x, tile_y, kchunk, s);
 }
 
 hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
@@ -1940,6 +1987,17 @@ hipError_t launch_defect(const double2* A, const double2* B, float2* R, const Pl
 hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long long N,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, S, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, Y, S, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double2* X, const double2* D, double w, long long S, long long N,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, S, N);
     return hipGetLastError();
 }
 

@@ -170,3 +170,46 @@ def test_adjoint_requires_adjoint_workspace():
         s.adjoint_grad(np.ones(pb.shape), tol=0.0, max_it=1)
     assert e.value.status == thiim.THIIM_EINVAL
     s.close()
+
+
+def test_adjoint_directional_fd_128x128x256():
+    """The gradient configuration at its full size: a 128 x 128 x 256 textured
+    stack (eps'' in [0.1, 0.5]), J over the cells of the middle layer, forward
+    and adjoint solved to 1e-10 (forward: the mixed-precision solver with a
+    fixed inner count; adjoint: averaged defect correction).  Check: the
+    central difference (h = 1e-6) of J along a seeded random direction of eps
+    over the middle layer -- both perturbed forward solves run the same sweep
+    schedule as the unperturbed one, so their truncation errors correlate --
+    against the gradient's inner product with it."""
+    _require_gpu()
+    pb = inputs.solar_cell(128, 128, 256, seed=20, npml=6, loss_range=(0.1, 0.5))
+    mid = pb.layers[1][2]
+    w = (pb.eps == mid).astype(np.float64)  # the middle layer's cells
+    assert w.sum() > 0
+    m = 2000
+    kw = dict(storage="compact", precision="mixed", t_block=3, adjoint=True)
+    s = thiim.Solver(pb, **kw)
+    rc, n_sw, r = s.solve(1e-10, 2000000, m)
+    assert rc == thiim.THIIM_OK, (n_sw, r)
+    print(f"[adjoint 128x128x256] forward {n_sw} sweeps", flush=True)
+    rc, J0, grad, ait, ar = s.adjoint_grad(w, tol=1e-10, max_it=2000000, check_every=m)
+    assert rc == thiim.THIIM_OK, (ait, ar)
+    print(f"[adjoint 128x128x256] adjoint {ait} sweeps", flush=True)
+    grad = grad.cpu().numpy()
+    s.close()
+    g = inputs.rng(25)
+    d = (g.standard_normal(pb.shape) + 1j * g.standard_normal(pb.shape)) * w
+    hfd = 1e-6
+
+    def J_at(eps):
+        p = inputs.Problem(**{**pb.__dict__, "eps": eps})
+        sp = thiim.Solver(p, **kw)
+        sp.solve(1e-30, n_sw, m)  # the same schedule, stopped at n_sw sweeps
+        out = sp.adjoint_grad(w, tol=0.0, max_it=0)[1]
+        sp.close()
+        return out
+
+    fd = (J_at(pb.eps + hfd * d) - J_at(pb.eps - hfd * d)) / (2 * hfd)
+    an = float(np.sum(grad.real * d.real + grad.imag * d.imag))
+    print(f"[adjoint 128x128x256] fd {fd:.10e} adjoint {an:.10e}", flush=True)
+    assert abs(fd - an) <= 1e-5 * abs(an)
