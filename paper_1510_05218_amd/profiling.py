@@ -11,11 +11,14 @@
 * ``run_mixed``: a GPU workload for profiling the complex64 inner sweeps --
   two defect-correction steps of the mixed-precision solver on the n^3
   benchmark problem, with T = 2 and with T = 3 inner passes.
+* ``run_solve``: time to relative residual 1e-8 on the n^3 benchmark
+  problem, mixed solver against the plain FP64 iteration.
 
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
     python -m paper_1510_05218_amd.profiling run_mixed [n]
+    python -m paper_1510_05218_amd.profiling run_solve [n]
 """
 from __future__ import annotations
 
@@ -161,6 +164,57 @@ def run_mixed(n=512):
         torch.cuda.empty_cache()
 
 
+def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
+    """Time to solution on the n^3 benchmark workload (textured, 200 lossless
+    spheres): the mixed solver (T = 3, 2000 inner sweeps per correction) to
+    tol, then the plain FP64 iteration to tol or fp64_budget iterations.  Both
+    run in slices so that every slice prints its progress."""
+    import time
+
+    import torch
+
+    from . import inputs, thiim
+
+    pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200 if n >= 128 else 0)
+    dev = inputs.Problem(**{**pb.__dict__})
+    dev.eps = torch.from_numpy(pb.eps).cuda()
+    dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
+    out = {"grid": f"{n}^3", "tol": tol}
+    m = 2000
+    s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=3)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    sweeps, r = 0, 1.0
+    while r > tol and sweeps < 400000:
+        rc, it, r = s.solve(tol, 3 * (m + 1), m)
+        sweeps += it
+        print(json.dumps({"mixed_sweeps": sweeps, "rel_res": r, "s": round(time.time() - t0, 1)}),
+              flush=True)
+    out["mixed"] = {"sweeps": sweeps, "rel_res": r, "seconds": time.time() - t0}
+    xm = s.fields()
+    pm = xm[0::2] + xm[1::2]
+    del xm
+    s.close()
+    torch.cuda.empty_cache()
+    s = thiim.Solver(dev, storage="compact")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    its, r = 0, 1.0
+    while r > tol and its < fp64_budget:
+        rc, it, r = s.solve(tol, 2000, 500)
+        its += it
+        print(json.dumps({"fp64_iterations": its, "rel_res": r, "s": round(time.time() - t0, 1)}),
+              flush=True)
+    out["fp64"] = {"iterations": its, "rel_res": r, "seconds": time.time() - t0}
+    x64 = s.fields()
+    p64 = x64[0::2] + x64[1::2]
+    del x64
+    out["physical_rel_diff"] = float(torch.linalg.vector_norm(pm - p64) /
+                                     torch.linalg.vector_norm(p64))
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main(argv):
     if argv[0] == "traffic":
         fetch, write, n, out, cmd = argv[1:6]
@@ -172,6 +226,8 @@ def main(argv):
         print(open(out).read())
     elif argv[0] == "run_mixed":
         run_mixed(int(argv[1]) if len(argv) > 1 else 512)
+    elif argv[0] == "run_solve":
+        run_solve_512(int(argv[1]) if len(argv) > 1 else 512)
     else:
         raise SystemExit(__doc__)
 
