@@ -13,12 +13,15 @@
   benchmark problem, with T = 2 and with T = 3 inner passes.
 * ``run_solve``: time to relative residual 1e-8 on the n^3 benchmark
   problem, mixed solver against the plain FP64 iteration.
+* ``run_spectral``: the full batched spectral sweep (32 wavelengths x 4
+  geometries up to 192 x 192 x 384) to 1e-8 in resident waves.
 
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
+    python -m paper_1510_05218_amd.profiling run_spectral [waves]
 """
 from __future__ import annotations
 
@@ -215,6 +218,56 @@ def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
     print(json.dumps(out), flush=True)
 
 
+SPECTRAL_GEOMETRIES = [(64, 64, 64, 10), (96, 96, 128, 11), (128, 128, 256, 12),
+                       (192, 192, 384, 13)]
+
+
+def run_spectral(waves_spec="0,1,2:3a:3b:3c", n_wl=32, tol=1e-8, m=2000):
+    """The batched spectral sweep: n_wl wavelengths 300-1100 nm x the four
+    seeded geometries, solved to tol by the batched mixed-precision solver in
+    resident waves (a wave is a list of geometry indices; '3a', '3b', '3c'
+    split geometry 3's wavelengths in three), each wave in slices of three
+    corrections so that every slice prints its progress."""
+    import time
+
+    import torch
+
+    from . import inputs, thiim
+
+    wls = [300.0 + 800.0 * i / (n_wl - 1) for i in range(n_wl)]
+    total_t, total_cells, solved = 0.0, 0, 0
+    for wave in waves_spec.split(":"):
+        probs = []
+        for part in wave.split(","):
+            gi = int(part[0])
+            sel = wls
+            if len(part) > 1:
+                j = "abc".index(part[1])
+                sel = wls[j::3]
+            nx, ny, nz, seed = SPECTRAL_GEOMETRIES[gi]
+            probs += [inputs.solar_cell(nx, ny, nz, seed=seed, npml=6, wavelength_nm=wl)
+                      for wl in sel]
+        cells = sum(p.eps.size for p in probs)
+        t0 = time.time()
+        bt = thiim.Batch(probs, precision="mixed", t_block=3)
+        res = None
+        while res is None or res.max() > tol:
+            rc, its, res = bt.solve(tol, 3 * (m + 1), m)
+            print(json.dumps({"wave": wave, "problems": len(probs), "converged":
+                              int((res <= tol).sum()), "max_res": float(res.max()),
+                              "s": round(time.time() - t0, 1)}), flush=True)
+        bt.synchronize()
+        dt = time.time() - t0
+        bt.close()
+        torch.cuda.empty_cache()
+        total_t += dt
+        total_cells += cells
+        solved += len(probs)
+        print(json.dumps({"wave_done": wave, "cells": cells, "seconds": dt}), flush=True)
+    print(json.dumps({"problems": solved, "cells": total_cells, "seconds": total_t,
+                      "solves_per_s": solved / total_t}), flush=True)
+
+
 def main(argv):
     if argv[0] == "traffic":
         fetch, write, n, out, cmd = argv[1:6]
@@ -228,6 +281,8 @@ def main(argv):
         run_mixed(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_solve":
         run_solve_512(int(argv[1]) if len(argv) > 1 else 512)
+    elif argv[0] == "run_spectral":
+        run_spectral(argv[1] if len(argv) > 1 else "0,1,2:3a:3b:3c")
     else:
         raise SystemExit(__doc__)
 
