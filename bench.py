@@ -120,6 +120,7 @@ def cpu_baseline(pb_full, budget_s=15.0):
     coef = oracle.coeffs(eps, pb_full.sig_e[:nzs].copy(), pb_full.sig_h[:nzs].copy(), src,
                          pb_full.omega, pb_full.tau)
     x = oracle.zero_fields(eps.shape)
+    oracle.iterate(coef, x, 1)  # warm-up (page-in, thread start)
     t = time.perf_counter()
     oracle.iterate(coef, x, 1)
     one = time.perf_counter() - t
@@ -127,13 +128,25 @@ def cpu_baseline(pb_full, budget_s=15.0):
     t = time.perf_counter()
     oracle.iterate(coef, x, n)
     dt = time.perf_counter() - t
+    cores = oracle.num_threads()
+    # one core, for reference (a few seconds)
+    oracle.set_threads(1)
+    t = time.perf_counter()
+    oracle.iterate(coef, x, 1)
+    one1 = time.perf_counter() - t
+    n1 = max(1, min(200, int(budget_s / 3 / max(one1, 1e-6))))
+    t = time.perf_counter()
+    oracle.iterate(coef, x, n1)
+    dt1 = time.perf_counter() - t
+    oracle.set_threads(cores)
     return {
         "value": eps.size * n / dt / 1e9,
         "unit": "GLUP/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{eps.shape[2]}x{eps.shape[1]}x{nzs} leading planes of the workload "
                   f"(28-array layout, C, OpenMP), {n} iterations in {dt:.1f} s",
+        "single_core_value": eps.size * n1 / dt1 / 1e9,
     }
 
 

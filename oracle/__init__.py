@@ -65,6 +65,8 @@ def _configure(lib):
     lib.oracle_flops_per_update.argtypes = [ctypes.c_int]
     lib.oracle_flops_per_update.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     return lib
 
 
@@ -92,6 +94,11 @@ def _ptr_array(arrs):
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loop nests (n >= 1)."""
+    _load().oracle_set_threads(int(n))
 
 
 def flops_per_update(has_src: bool) -> int:

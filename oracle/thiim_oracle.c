@@ -388,6 +388,15 @@ int oracle_adjoint_iterate(int nx, int ny, int nz, int bcx, int bcy,
 /* Flop count of one component update, as written above (Listings 1/2). */
 int oracle_flops_per_update(int has_src) { return has_src ? 22 : 20; }
 
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -299,3 +299,54 @@ def test_pml_and_loss_damp(oracle_lib):
     for q in range(6, 12):  # E damped by the material loss everywhere
         assert np.all(np.abs(coef[q]) < 1)
     assert np.all(np.abs(coef[:12]) <= 1 + 1e-15)
+
+
+# --------------------------------------------------------------------------
+# The undamped modes (R16, R17): one iteration multiplies a curl-free H with
+# no E, and (in lossless cells) a curl-free E with no H, by exactly
+# e^{-i w tau}.  These are the modes the mixed solver's window averaging
+# targets; the pin checks the claim against the oracle's iteration.
+# --------------------------------------------------------------------------
+def _grad_field(phi, backward):
+    """Components (x, y, z) of the discrete gradient of phi (nz, ny, nx),
+    periodic in x/y: forward differences phi(p + e) - phi(p), or backward."""
+    out = []
+    for ax in (2, 1, 0):  # x, y, z axes of the array
+        if backward:
+            out.append(phi - np.roll(phi, 1, axis=ax))
+        else:
+            out.append(np.roll(phi, -1, axis=ax) - phi)
+    return out
+
+
+@pytest.mark.parametrize("field", ["H", "E"])
+def test_curl_free_fields_rotate_by_exp_minus_i_omega_tau(oracle_lib, field):
+    pb = inputs.random_problem(8, 7, 16, seed=17, npml=3)
+    if field == "E":
+        pb.eps = pb.eps.real + 0j  # lossless cells
+    coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, {}, pb.omega, pb.tau, pb.h)
+    g = inputs.rng(18)
+    phi = g.standard_normal(pb.shape) + 1j * g.standard_normal(pb.shape)
+    phi[:5] = 0.0  # zero in and next to the PML planes and the z walls
+    phi[-5:] = 0.0
+    comps = _grad_field(phi, backward=(field == "E"))
+    x = oracle.zero_fields(pb.shape)
+    base = 0 if field == "H" else 6
+    for a in range(3):
+        split = g.uniform(0, 1, pb.shape)  # any division between the two parts
+        x[base + 2 * a] = split * comps[a]
+        x[base + 2 * a + 1] = (1 - split) * comps[a]
+    lam = np.exp(-1j * pb.omega * pb.tau)
+    # physical fields: the other field's split parts become equal and opposite
+    # (a split-difference mode, invisible in P), the curl-free field rotates
+    y = P(oracle.phi(coef, x))
+    assert np.linalg.norm(y - lam * P(x)) <= 1e-14 * np.linalg.norm(P(x))
+    # a gradient that reaches into the PML decays there instead
+    if field == "H":
+        phi2 = g.standard_normal(pb.shape) + 0j
+        comps = _grad_field(phi2, backward=False)
+        x2 = oracle.zero_fields(pb.shape)
+        for a in range(3):
+            x2[2 * a] = comps[a]
+        y2 = P(oracle.phi(coef, x2))
+        assert np.linalg.norm(y2 - lam * P(x2)) > 1e-3 * np.linalg.norm(P(x2))
