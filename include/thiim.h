@@ -181,7 +181,9 @@ int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
  *             modes an iteration rotates by e^{-i omega tau}; the plain
  *             transposed iteration converges much more slowly where the PML
  *             conductivity is small), until tol or max_it sweeps
- *             (THIIM_ENOTCONV; the outputs are still written)
+ *             (THIIM_ENOTCONV; the outputs are still written).  On a
+ *             THIIM_PRECISION_MIXED context the inner sweeps run in
+ *             complex64; the defect, lam and the norms stay in FP64.
  *   tol <= 0  exactly max_it plain transposed iterations lam <- M^T lam + g
  *             from lam = 0 (check_every unused)
  *   grad_eps  device, 2*N doubles: (dJ/deps', dJ/deps'') per cell

@@ -621,13 +621,30 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
             if (std::isfinite(prev) && r > 0.3 * prev && m < (1 << 15)) m *= 2;
             prev = r;
             e = thiim::launch_sub(c->lam[0], c->lam[1], S, N, c->stream);  // r
-            if (e == hipSuccess) e = thiim::launch_copy(c->lam[1], c->lam[2], 12 * S, c->stream);
-            int di = 2;
-            for (int p = 0; e == hipSuccess && p < m; ++p) {
-                e = sweep(di, 5 - di, c->lam[1], true);
-                di = 5 - di;
-                if (e == hipSuccess && p >= m - Kp)
-                    e = thiim::launch_axpy(c->lam[0], c->lam[di], 1.0 / Kp, S, N, c->stream);
+            if (c->ce32) {
+                // mixed-precision context: complex64 inner sweeps (its r32 and
+                // d32 buffers), the defect and lam in FP64
+                if (e == hipSuccess) e = thiim::launch_to32(c->lam[1], c->r32, S, N, c->stream);
+                if (e == hipSuccess) e = thiim::launch_copy32(c->r32, c->d32[0], S, N, c->stream);
+                int di = 0;
+                for (int p = 0; e == hipSuccess && p < m; ++p) {
+                    e = thiim::launch_adjoint32(c->cv, c->ce32, c->p32, c->d32[di],
+                                                c->d32[1 - di], c->r32, c->geo, c->tile_x,
+                                                c->tile_y, c->z_chunk, c->stream);
+                    di = 1 - di;
+                    if (e == hipSuccess && p >= m - Kp)
+                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kp, S, N, c->stream);
+                }
+            } else {
+                if (e == hipSuccess)
+                    e = thiim::launch_copy(c->lam[1], c->lam[2], 12 * S, c->stream);
+                int di = 2;
+                for (int p = 0; e == hipSuccess && p < m; ++p) {
+                    e = sweep(di, 5 - di, c->lam[1], true);
+                    di = 5 - di;
+                    if (e == hipSuccess && p >= m - Kp)
+                        e = thiim::launch_axpy(c->lam[0], c->lam[di], 1.0 / Kp, S, N, c->stream);
+                }
             }
             if (e != hipSuccess) return hip_fail(e, "adjoint: correction");
             done += m;

@@ -131,8 +131,14 @@ hipError_t launch_resid(const double2* A, const double2* B, long long S, long lo
 hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, const double2* G,
                           bool dense, const Geo& g, int tile_x, int tile_y, int kchunk,
                           hipStream_t s);
+// Complex64 transposed sweep with a 12-array source R (inner sweeps of the
+// adjoint defect correction on mixed-precision contexts).
+hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                            const float2* A, float2* B, const float2* R, const Geo& g,
+                            int tile_x, int tile_y, int kchunk, hipStream_t s);
 // 12-array FP64 helpers: Y -= X; X += w D.
 hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s);
+hipError_t launch_to32(const double2* X, float2* R, long long S, long long N, hipStream_t s);
 hipError_t launch_axpy(double2* X, const double2* D, double w, long long S, long long N,
                        hipStream_t s);
 hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,

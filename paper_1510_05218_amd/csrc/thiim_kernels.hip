@@ -96,6 +96,9 @@ constexpr int kBlockedStrip = 4;
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 __device__ __forceinline__ double2 cdiv(double2 a, double2 d) {
     double den = d.x * d.x + d.y * d.y;
     return make_double2((a.x * d.x + a.y * d.y) / den, (a.y * d.x - a.x * d.y) / den);
@@ -1290,14 +1293,52 @@ __global__ __launch_bounds__(256) void k_resid_final(const double* __restrict__ 
 // k_adjoint has the structure of k_fused: tile + halo ring through LDS, z
 // streamed, step 2 one plane behind step 1.
 // ---------------------------------------------------------------------------
-// DENSE = false: G holds g_a (3 arrays), added to both parts of E_a;
-// DENSE = true:  G holds a source for every part (12 arrays), added to each
-//                part after its transposed update (lam <- M^T lam + G).
-template <int TX, int TY, class CP, bool DENSE>
-__global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __restrict__ A,
-                                                    double2* __restrict__ B,
-                                                    const double2* __restrict__ G, Geo g,
+// Adjoint policies: the complex type and the coefficients of the transposed
+// sweep.  AdjPol64: complex128, coefficients from eps (the forward sweeps'
+// functions); AdjPol32: complex64 inner sweeps of the adjoint defect
+// correction, coefficients from the complex64 records (k_prep32).
+//   DENSE = false: G holds g_a (3 arrays), added to both parts of E_a;
+//   DENSE = true:  G holds a source for every part (12 arrays), added to each
+//                  part after its transposed update (lam <- M^T lam + G).
+template <bool D>
+struct AdjPol64 {
+    using V = double2;
+    static constexpr bool DENSE = D;
+    CompactCoefs cp;
+    __device__ __forceinline__ void ecoef(int k, long long po, uint32_t bo, V t[6],
+                                          V c[6]) const {
+        double2 sa, sb;
+        cp.e(k, po, bo, t, c, sa, sb);
+    }
+    __device__ __forceinline__ void hcoef(int k, V t[6], V c[6]) const {
+        const PlaneCoef pc = cp.P[k];
+        t[0] = pc.thz; c[0] = pc.chz;
+        t[1] = pc.th0; c[1] = pc.ch0;
+        t[2] = pc.thz; c[2] = pc.chz;
+        t[3] = pc.th0; c[3] = pc.ch0;
+        t[4] = pc.th0; c[4] = pc.ch0;
+        t[5] = pc.th0; c[5] = pc.ch0;
+    }
+};
+
+struct AdjPol32 {
+    using V = float2;
+    static constexpr bool DENSE = true;
+    Pol32 p;  // records, plane table and phases (its sources are unused)
+    __device__ __forceinline__ void ecoef(int k, long long po, uint32_t bo, V t[6],
+                                          V c[6]) const {
+        p.ecoef_c(k, p.load_crec(po, bo), t, c);
+    }
+    __device__ __forceinline__ void hcoef(int k, V t[6], V c[6]) const { p.hcoef_c(k, t, c); }
+};
+
+template <int TX, int TY, class AP>
+__global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V* __restrict__ A,
+                                                    typename AP::V* __restrict__ B,
+                                                    const typename AP::V* __restrict__ G, Geo g,
                                                     int kchunk) {
+    using V = typename AP::V;
+    constexpr bool DENSE = AP::DENSE;
     constexpr int NT = TX * TY;
     constexpr int EW = TX + 2, EH = TY + 2;  // u region [-1,TX] x [-1,TY]
     constexpr int HW = TX + 1, HH = TY + 1;  // lam_H' region [0,TX] x [0,TY]
@@ -1305,8 +1346,8 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
     constexpr int NHH = TX + TY + 1;
     constexpr int NEH = NE - NT;
     static_assert(NEH <= NT, "halo larger than tile");
-    __shared__ double2 Us[4][NE];  // u1, u3, u4, u5 of plane k
-    __shared__ double2 Vs[4][NH];  // v1, v3, v4, v5 of plane k-1
+    __shared__ V Us[4][NE];  // u1, u3, u4, u5 of plane k
+    __shared__ V Vs[4][NH];  // v1, v3, v4, v5 of plane k-1
 
     const long long S = g.S;
     const int tid = threadIdx.x;
@@ -1338,24 +1379,25 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
     const bool halo_valid = has_eh && resolve_xy(g, hgi, hgj);
     const uint32_t bh = halo_valid ? 16u * (uint32_t)(hgj * g.nx + hgi) : 0u;
 
-    const double2* AE = A + 6 * S;
-    double2* BE = B + 6 * S;
+    const V* AE = A + 6 * S;
+    V* BE = B + 6 * S;
+    const V Z = vzero<V>();
 
-    double2 ep[6], vp[6];  // own t_E lam_E and v of plane k-1
+    V ep[6], vp[6];  // own t_E lam_E and v of plane k-1
 #pragma unroll
-    for (int q = 0; q < 6; ++q) ep[q] = vp[q] = czero();
-    double2 u0m = czero(), u2m = czero();    // own u0, u2 of plane k-1
-    double2 hu0m = czero(), hu2m = czero();  // the halo cell's u0, u2 of plane k-1
+    for (int q = 0; q < 6; ++q) ep[q] = vp[q] = Z;
+    V u0m = Z, u2m = Z;    // own u0, u2 of plane k-1
+    V hu0m = Z, hu2m = Z;  // the halo cell's u0, u2 of plane k-1
     if (k0 > 0) {
         const long long po = (k0 - 1) * plane;
-        double2 t[6], c[6], sa, sb;
+        V t[6], c[6];
         if (own_valid) {
-            cp.e(k0 - 1, po, bo, t, c, sa, sb);
+            ap.ecoef(k0 - 1, po, bo, t, c);
             u0m = cmul(c[0], ldo(AE + 0 * S + po, bo));
             u2m = cmul(c[2], ldo(AE + 2 * S + po, bo));
         }
         if (has_hh && halo_valid) {
-            cp.e(k0 - 1, po, bh, t, c, sa, sb);
+            ap.ecoef(k0 - 1, po, bh, t, c);
             hu0m = cmul(c[0], ldo(AE + 0 * S + po, bh));
             hu2m = cmul(c[2], ldo(AE + 2 * S + po, bh));
         }
@@ -1364,16 +1406,16 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
     for (int k = k0; k <= k1; ++k) {
         const bool plane_in = k < g.nz;
         const long long po = k * plane;
-        double2 u[6], en[6];
+        V u[6], en[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) u[q] = en[q] = czero();
-        double2 hu0 = czero(), hu2 = czero();
+        for (int q = 0; q < 6; ++q) u[q] = en[q] = Z;
+        V hu0 = Z, hu2 = Z;
         // ---- phase 1: u = c_E lam_E of plane k; u1, u3, u4, u5 into LDS
         if (plane_in) {
             if (own_valid) {
-                double2 l[6], t[6], c[6], sa, sb;
-                load6(AE, S, po, bo, l);
-                cp.e(k, po, bo, t, c, sa, sb);
+                V l[6], t[6], c[6];
+                load6v(AE, S, po, bo, l);
+                ap.ecoef(k, po, bo, t, c);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
                     u[q] = cmul(c[q], l[q]);
@@ -1385,13 +1427,13 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
             Us[2][eo] = u[4];
             Us[3][eo] = u[5];
             if (has_eh) {
-                double2 hu[6];
+                V hu[6];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) hu[q] = czero();
+                for (int q = 0; q < 6; ++q) hu[q] = Z;
                 if (halo_valid) {
-                    double2 l[6], t[6], c[6], sa, sb;
-                    load6(AE, S, po, bh, l);
-                    cp.e(k, po, bh, t, c, sa, sb);
+                    V l[6], t[6], c[6];
+                    load6v(AE, S, po, bh, l);
+                    ap.ecoef(k, po, bh, t, c);
 #pragma unroll
                     for (int q = 0; q < 6; ++q) hu[q] = cmul(c[q], l[q]);
                 }
@@ -1405,22 +1447,22 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
         }
         __syncthreads();
         // ---- phase 2: lam_H' of plane k on the tile and the +x / +y ring
-        double2 v[6];
+        V v[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = czero();
-        double2 hv1 = czero(), hv3 = czero(), hv4 = czero(), hv5 = czero();
+        for (int q = 0; q < 6; ++q) v[q] = Z;
+        V hv1 = Z, hv3 = Z, hv4 = Z, hv5 = Z;
         if (plane_in) {
             if (own_valid) {
-                const double2 inc[3] = {
+                const V inc[3] = {
                     csub(csub(u2m, u[2]), csub(Us[2][eo - EW], u[4])),
                     csub(csub(Us[3][eo - 1], u[5]), csub(u0m, u[0])),
                     csub(csub(Us[0][eo - EW], u[1]), csub(Us[1][eo - 1], u[3]))};
-                double2 l[6], t[6], c[6], sa, sb;
-                load6(A, S, po, bo, l);
-                cp.h(k, po, bo, t, c, sa, sb);
+                V l[6], t[6], c[6];
+                load6v(A, S, po, bo, l);
+                ap.hcoef(k, t, c);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
-                    const double2 lh = cadd(l[q], inc[q / 2]);
+                    const V lh = cadd(l[q], inc[q / 2]);
                     v[q] = cmul(c[q], lh);
                     l[q] = cmul(t[q], lh);
                 }
@@ -1429,17 +1471,17 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
 #pragma unroll
                         for (int q = 0; q < 6; ++q) l[q] = cadd(l[q], ldo(G + q * S + po, bo));
                     }
-                    store6(B, S, po, bo, l);
+                    store6v(B, S, po, bo, l);
                 }
             }
             if (has_hh && halo_valid) {
-                const double2 inc[3] = {
+                const V inc[3] = {
                     csub(csub(hu2m, hu2), csub(Us[2][eh - EW], Us[2][eh])),
                     csub(csub(Us[3][eh - 1], Us[3][eh]), csub(hu0m, hu0)),
                     csub(csub(Us[0][eh - EW], Us[0][eh]), csub(Us[1][eh - 1], Us[1][eh]))};
-                double2 l[6], t[6], c[6], sa, sb;
-                load6(A, S, po, bh, l);
-                cp.h(k, po, bh, t, c, sa, sb);
+                V l[6], t[6], c[6];
+                load6v(A, S, po, bh, l);
+                ap.hcoef(k, t, c);
                 hv1 = cmul(c[1], cadd(l[1], inc[0]));
                 hv3 = cmul(c[3], cadd(l[3], inc[1]));
                 hv4 = cmul(c[4], cadd(l[4], inc[2]));
@@ -1449,11 +1491,11 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
         // ---- phase 3: lam_E of plane k-1 on the own cell
         if (k > k0 && own_valid) {
             const long long pm = po - plane;
-            double2 inc[3] = {
+            V inc[3] = {
                 csub(csub(vp[4], Vs[2][ho + HW]), csub(vp[2], v[2])),
                 csub(csub(vp[0], v[0]), csub(vp[5], Vs[3][ho + 1])),
                 csub(csub(vp[3], Vs[1][ho + 1]), csub(vp[1], Vs[0][ho + HW]))};
-            double2 out[6];
+            V out[6];
             if constexpr (DENSE) {
 #pragma unroll
                 for (int q = 0; q < 6; ++q)
@@ -1464,7 +1506,7 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(CP cp, const double2* __rest
 #pragma unroll
                 for (int q = 0; q < 6; ++q) out[q] = cadd(ep[q], inc[q / 2]);
             }
-            if (own_store) store6(BE, S, pm, bo, out);
+            if (own_store) store6v(BE, S, pm, bo, out);
         }
         __syncthreads();
         // ---- phase 4: v of plane k into LDS, shift the z state
@@ -1700,6 +1742,19 @@ __global__ void k_sub(const double2* __restrict__ X, double2* __restrict__ Y, lo
     }
 }
 
+// R = X rounded to complex64, 12 arrays
+__global__ void k_to32(const double2* __restrict__ X, float2* __restrict__ R, long long S,
+                       long long N) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double2 x = X[q * S + p];
+            R[q * S + p] = make_float2((float)x.x, (float)x.y);
+        }
+    }
+}
+
 // X += w D over 12 arrays (FP64)
 __global__ void k_axpy(double2* __restrict__ X, const double2* __restrict__ D, double w,
                        long long S, long long N) {
@@ -1861,23 +1916,23 @@ hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total,
     return hipGetLastError();
 }
 
-template <bool DENSE>
-static hipError_t adjoint_impl(const CompactCoefs& cp, const double2* A, double2* B,
-                               const double2* G, const Geo& g, int tile_x, int tile_y,
+template <class AP>
+static hipError_t adjoint_impl(const AP& cp, const typename AP::V* A, typename AP::V* B,
+                               const typename AP::V* G, const Geo& g, int tile_x, int tile_y,
                                int kchunk, hipStream_t s) {
     dim3 grid(((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y) *
               nchunks(g, kchunk));
     if (tile_x == 64 && tile_y == 8)
-        hipLaunchKernelGGL((k_adjoint<64, 8, CompactCoefs, DENSE>), grid, dim3(512), 0, s, cp, A,
+        hipLaunchKernelGGL((k_adjoint<64, 8, AP>), grid, dim3(512), 0, s, cp, A,
                            B, G, g, kchunk);
     else if (tile_x == 32 && tile_y == 8)
-        hipLaunchKernelGGL((k_adjoint<32, 8, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp, A,
+        hipLaunchKernelGGL((k_adjoint<32, 8, AP>), grid, dim3(256), 0, s, cp, A,
                            B, G, g, kchunk);
     else if (tile_x == 64 && tile_y == 4)
-        hipLaunchKernelGGL((k_adjoint<64, 4, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp, A,
+        hipLaunchKernelGGL((k_adjoint<64, 4, AP>), grid, dim3(256), 0, s, cp, A,
                            B, G, g, kchunk);
     else if (tile_x == 16 && tile_y == 16)
-        hipLaunchKernelGGL((k_adjoint<16, 16, CompactCoefs, DENSE>), grid, dim3(256), 0, s, cp,
+        hipLaunchKernelGGL((k_adjoint<16, 16, AP>), grid, dim3(256), 0, s, cp,
                            A, B, G, g, kchunk);
     else
         return hipErrorInvalidValue;
@@ -1889,8 +1944,24 @@ hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, cons
                           hipStream_t s) {
     if (!cv.compact) return hipErrorInvalidValue;
     const CompactCoefs cp = compact_of(cv);
-    return dense ? adjoint_impl<true>(cp, A, B, G, g, tile_x, tile_y, kchunk, s)
-                 : adjoint_impl<false>(cp, A, B, G, g, tile_x, tile_y, kchunk, s);
+    return dense ? adjoint_impl(AdjPol64<true>{cp}, A, B, G, g, tile_x, tile_y, kchunk, s)
+                 : adjoint_impl(AdjPol64<false>{cp}, A, B, G, g, tile_x, tile_y, kchunk, s);
+}
+
+hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                            const float2* A, float2* B, const float2* R, const Geo& g,
+                            int tile_x, int tile_y, int kchunk, hipStream_t s) {
+    if (!cv.compact) return hipErrorInvalidValue;
+    AdjPol32 ap;
+    ap.p.ce = ce;
+    ap.p.P32 = P32;
+    ap.p.r = nullptr;
+    ap.p.S = cv.S;
+    ap.p.ph = to32(cv.K.ph);
+    ap.p.phc = to32(cv.K.phc);
+    ap.p.ph2 = to32(cv.K.ph2);
+    ap.p.ph2c = to32(cv.K.ph2c);
+    return adjoint_impl(ap, A, B, R, g, tile_x, tile_y, kchunk, s);
 }
 
 hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
@@ -1992,6 +2063,11 @@ hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long
 
 hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s) {
     hipLaunchKernelGGL(k_sub, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, Y, S, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_to32(const double2* X, float2* R, long long S, long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_to32, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, R, S, N);
     return hipGetLastError();
 }
 

@@ -213,3 +213,24 @@ def test_adjoint_directional_fd_128x128x256():
     an = float(np.sum(grad.real * d.real + grad.imag * d.imag))
     print(f"[adjoint 128x128x256] fd {fd:.10e} adjoint {an:.10e}", flush=True)
     assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+def test_adjoint_on_mixed_context_matches_fp64():
+    """On a mixed-precision context the adjoint's inner sweeps run in
+    complex64 (defect, lam and norms in FP64): to the same tolerance the
+    gradient equals the one from an FP64 context."""
+    _require_gpu()
+    pb = inputs.random_problem(24, 20, 28, seed=95, all_sources=False)
+    w = inputs.rng(96).uniform(0, 1, pb.shape)
+    grads = []
+    for prec in ("fp64", "mixed"):
+        s = thiim.Solver(pb, storage="compact", precision=prec, adjoint=True)
+        rc, it, r = s.solve(1e-12, 400000, 300 if prec == "mixed" else 100)
+        assert rc == thiim.THIIM_OK, (prec, it, r)
+        rc, J, grad, ait, ar = s.adjoint_grad(w, tol=1e-12, max_it=400000, check_every=300)
+        assert rc == thiim.THIIM_OK, (prec, ait, ar)
+        print(f"[adjoint {prec}] forward {it}, adjoint {ait} sweeps", flush=True)
+        grads.append(grad.cpu().numpy())
+        s.close()
+    scale = np.abs(grads[0]).max()
+    assert np.abs(grads[1] - grads[0]).max() <= 1e-8 * scale
