@@ -11,6 +11,8 @@ Contents
   * ``coeffs``    -- the 28 coefficient arrays from the material data
                      (Eq. 3-5 solved for the new value; C, ``thiim_oracle.c``)
   * ``iterate``   -- n THIIM iterations, the 12 loop nests of Listings 1/2 (C)
+  * ``iterate_light`` -- the same without coefficient arrays (memory-light
+                     mode for full-size grids; bit-identical)
   * ``residual``  -- ||P(Phi(x) - x)||_2 / ||P Phi(0)||_2 in FP64, P the sum
                      of each split pair (the physical field)
   * ``dense``     -- the time-harmonic fixed-point system assembled directly
@@ -59,6 +61,10 @@ def _configure(lib):
     lib.oracle_iterate.argtypes = [ctypes.c_int] * 5 + [
         ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.c_int]
     lib.oracle_iterate.restype = ctypes.c_int
+    lib.oracle_iterate_light.argtypes = [ctypes.c_int] * 5 + [
+        dp, dp, dp, ctypes.POINTER(dp), ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.POINTER(dp), ctypes.c_int]
+    lib.oracle_iterate_light.restype = ctypes.c_int
     lib.oracle_adjoint_iterate.argtypes = [ctypes.c_int] * 5 + [
         ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.c_int]
     lib.oracle_adjoint_iterate.restype = ctypes.c_int
@@ -142,6 +148,28 @@ def iterate(coef, fields, n, bcx=0, bcy=0):
     _load().oracle_iterate(nx, ny, nz, int(bcx), int(bcy),
                            _ptr_array([coef[i] for i in range(28)]),
                            _ptr_array([fields[i] for i in range(12)]), int(n))
+    return fields
+
+
+def iterate_light(eps, sig_e, sig_h, sources, omega, tau, h, fields, n, bcx=0, bcy=0):
+    """n THIIM iterations in place without coefficient arrays (memory-light
+    mode: coefficients evaluated per cell from the material data); bit-
+    identical to coeffs() + iterate()."""
+    eps = np.ascontiguousarray(eps, dtype=np.complex128)
+    nz, ny, nx = eps.shape
+    assert fields.shape == (12, nz, ny, nx) and fields.flags["C_CONTIGUOUS"]
+    sig_e = np.ascontiguousarray(sig_e, dtype=np.float64)
+    sig_h = np.ascontiguousarray(sig_h, dtype=np.float64)
+    src = []
+    for key in SRC_KEYS:
+        s = (sources or {}).get(key)
+        src.append(None if s is None else np.ascontiguousarray(s, dtype=np.complex128))
+    rc = _load().oracle_iterate_light(nx, ny, nz, int(bcx), int(bcy), _ptr(eps), _ptr(sig_e),
+                                      _ptr(sig_h), _ptr_array(src), float(omega), float(tau),
+                                      float(h), _ptr_array([fields[i] for i in range(12)]),
+                                      int(n))
+    if rc != 0:
+        raise ValueError("oracle_iterate_light: invalid material data")
     return fields
 
 

@@ -126,14 +126,19 @@ static long nbr(const grid_t *g, int k, int j, int i, int axis, int dir)
  *       = -(curl E^n) - sigma* H^{n+1/2} + S_H
  *   => H^{n+1/2} = t H^{n-1/2} + s c dE + Src, d = e^{iwt/2} + tau sigma*,
  *      t = e^{-iwt/2} / d,  c = (tau / h) / d,  Src = tau S_H / d. */
-static void coef_h(double omega, double tau, double h, double sig_star,
-                   double complex *t, double complex *c, double complex *sscale)
+static void coef_h_ph(double complex ph2, double tau, double h, double sig_star,
+                      double complex *t, double complex *c, double complex *sscale)
 {
-    double complex ph2 = cexp(I * (omega * tau / 2.0));
     double complex d = ph2 + tau * sig_star;
     *t = conj(ph2) / d;
     *c = (tau / h) / d;
     *sscale = tau / d;
+}
+
+static void coef_h(double omega, double tau, double h, double sig_star,
+                   double complex *t, double complex *c, double complex *sscale)
+{
+    coef_h_ph(cexp(I * (omega * tau / 2.0)), tau, h, sig_star, t, c, sscale);
 }
 
 /* E update.  Forward iteration, Eq. (3), for eps' > 0:
@@ -146,11 +151,10 @@ static void coef_h(double omega, double tau, double h, double sig_star,
  *       = (1/eps) curl H e^{iwt/2} - (sigma/eps) E^{n+1} + S_E
  *   => d = 1 - tau sigma / eps,  t = e^{iwt} / d,
  *      c = -(tau / (eps h)) e^{iwt/2} / d,  Src = -tau S_E / d. */
-static void coef_e(double omega, double tau, double h, double eps, double sigma,
-                   double complex *t, double complex *c, double complex *sscale)
+static void coef_e_ph(double complex ph, double complex ph2, double tau, double h,
+                      double eps, double sigma, double complex *t, double complex *c,
+                      double complex *sscale)
 {
-    double complex ph = cexp(I * (omega * tau));
-    double complex ph2 = cexp(I * (omega * tau / 2.0));
     if (eps > 0.0) {
         double d = 1.0 + tau * sigma / eps;
         *t = conj(ph) / d;
@@ -162,6 +166,13 @@ static void coef_e(double omega, double tau, double h, double eps, double sigma,
         *c = -(tau / (eps * h)) * ph2 / d;
         *sscale = -tau / d;
     }
+}
+
+static void coef_e(double omega, double tau, double h, double eps, double sigma,
+                   double complex *t, double complex *c, double complex *sscale)
+{
+    coef_e_ph(cexp(I * (omega * tau)), cexp(I * (omega * tau / 2.0)), tau, h, eps, sigma,
+              t, c, sscale);
 }
 
 static void put(double *a, long p, double complex v)
@@ -218,6 +229,52 @@ int oracle_coeffs(int nx, int ny, int nz, const double *eps,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Where an update finds t, c and Src of a part at a cell: the 28 stored   */
+/* arrays, or (memory-light mode) the same formulas evaluated on the fly   */
+/* from eps, the PML profiles and the raw sources.  Both modes call the    */
+/* same coefficient functions with the same phase factors, so they agree   */
+/* bit for bit.                                                            */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    const double *tq, *cq, *srcq; /* stored mode (srcq NULL: no source) */
+    int light;
+    const double *eps, *sig_e, *sig_h, *S; /* light mode (S NULL: zero) */
+    double complex ph, ph2;
+    double omega, tau, h;
+} csrc_t;
+
+/* t, c and Src of part q at cell p of plane k; returns whether the part has
+ * a source term. */
+static int coef_at(const csrc_t *cs, int q, int k, long p, double *tr, double *ti,
+                   double *cr, double *ci, double *sr, double *si)
+{
+    const comp_t *cm = &COMP[q];
+    if (!cs->light) {
+        *tr = cs->tq[2 * p]; *ti = cs->tq[2 * p + 1];
+        *cr = cs->cq[2 * p]; *ci = cs->cq[2 * p + 1];
+        if (!cs->srcq) return 0;
+        *sr = cs->srcq[2 * p]; *si = cs->srcq[2 * p + 1];
+        return 1;
+    }
+    double complex t, c, s;
+    if (q < 6) {
+        double sst = (cm->axis == 2) ? cs->sig_h[k] : 0.0;
+        coef_h_ph(cs->ph2, cs->tau, cs->h, sst, &t, &c, &s);
+    } else {
+        double sg = cs->omega * cs->eps[2 * p + 1] + ((cm->axis == 2) ? cs->sig_e[k] : 0.0);
+        coef_e_ph(cs->ph, cs->ph2, cs->tau, cs->h, cs->eps[2 * p], sg, &t, &c, &s);
+    }
+    *tr = creal(t); *ti = cimag(t);
+    *cr = creal(c); *ci = cimag(c);
+    if (cm->src < 0) return 0;
+    double complex S = 0.0;
+    if (cs->S) S = cs->S[2 * p] + I * cs->S[2 * p + 1];
+    double complex v = s * S;
+    *sr = creal(v); *si = cimag(v);
+    return 1;
+}
+
+/* ---------------------------------------------------------------------- */
 /* The 12 loop nests (Listings 1 and 2).                                   */
 /* ---------------------------------------------------------------------- */
 
@@ -227,10 +284,8 @@ int oracle_coeffs(int nx, int ny, int nz, const double *eps,
  *   H: backward difference, E: forward difference along the component axis.
  * With s the curl sign:  s c (G(p) - G(p-e)) = -c D  =>  D = -s (G(p) - G(p-e))
  * for H, and D = -s (G(p+e) - G(p)) for E. */
-static void update_component(const grid_t *g, int q, double *F,
-                             const double *tq, const double *cq,
-                             const double *srcq, const double *G1,
-                             const double *G2)
+static void update_component(const grid_t *g, int q, double *F, const csrc_t *cs,
+                             const double *G1, const double *G2)
 {
     const comp_t *cm = &COMP[q];
     const int is_h = q < 6;
@@ -264,12 +319,12 @@ static void update_component(const grid_t *g, int q, double *F,
                 double Re = a1 - b1 + a2 - b2;
                 double Im = a1i - b1i + a2i - b2i;
                 double fr = F[2 * p], fi = F[2 * p + 1];
-                double tr = tq[2 * p], ti = tq[2 * p + 1];
-                double cr = cq[2 * p], ci = cq[2 * p + 1];
+                double tr, ti, cr, ci, sr = 0.0, si = 0.0;
+                int has_src = coef_at(cs, q, k, p, &tr, &ti, &cr, &ci, &sr, &si);
                 double t;
-                if (srcq) {
-                    t = fr * tr - fi * ti + srcq[2 * p] - cr * Re + ci * Im;
-                    F[2 * p + 1] = fr * ti + fi * tr + srcq[2 * p + 1] - cr * Im - ci * Re;
+                if (has_src) {
+                    t = fr * tr - fi * ti + sr - cr * Re + ci * Im;
+                    F[2 * p + 1] = fr * ti + fi * tr + si - cr * Im - ci * Re;
                 } else {
                     t = fr * tr - fi * ti - cr * Re + ci * Im;
                     F[2 * p + 1] = fr * ti + fi * tr - cr * Im - ci * Re;
@@ -291,8 +346,49 @@ int oracle_iterate(int nx, int ny, int nz, int bcx, int bcy,
             for (int q = 6 * half; q < 6 * half + 6; q++) {
                 const comp_t *cm = &COMP[q];
                 const double *srcq = cm->src >= 0 ? coef[24 + cm->src] : NULL;
-                update_component(&g, q, F[q], coef[q], coef[12 + q], srcq,
-                                 F[cm->g1], F[cm->g2]);
+                csrc_t cs = {0};
+                cs.tq = coef[q];
+                cs.cq = coef[12 + q];
+                cs.srcq = srcq;
+                update_component(&g, q, F[q], &cs, F[cm->g1], F[cm->g2]);
+            }
+        }
+    }
+    return 0;
+}
+
+/* n THIIM iterations in memory-light mode: no coefficient arrays, t, c and
+ * Src evaluated per cell from eps (2*N), the PML profiles (nz each) and the
+ * raw sources (4 pointers S_Hx, S_Hy, S_Ex, S_Ey, 2*N each, or NULL).
+ * Bit-identical to oracle_coeffs + oracle_iterate; about 40 B of inputs per
+ * cell instead of 448. */
+int oracle_iterate_light(int nx, int ny, int nz, int bcx, int bcy, const double *eps,
+                         const double *sig_e, const double *sig_h,
+                         const double *const *src, double omega, double tau, double h,
+                         double *const *F, int n)
+{
+    grid_t g = {nx, ny, nz, bcx, bcy};
+    long N = (long)nx * ny * nz;
+    for (long p = 0; p < N; p++) {
+        double ep = eps[2 * p], epp = eps[2 * p + 1];
+        if (!(ep != 0.0) || !isfinite(ep) || !isfinite(epp)) return -1;
+    }
+    for (int it = 0; it < n; it++) {
+        for (int half = 0; half < 2; half++) {
+            for (int q = 6 * half; q < 6 * half + 6; q++) {
+                const comp_t *cm = &COMP[q];
+                csrc_t cs = {0};
+                cs.light = 1;
+                cs.eps = eps;
+                cs.sig_e = sig_e;
+                cs.sig_h = sig_h;
+                cs.S = (cm->src >= 0 && src) ? src[cm->src] : NULL;
+                cs.ph = cexp(I * (omega * tau));
+                cs.ph2 = cexp(I * (omega * tau / 2.0));
+                cs.omega = omega;
+                cs.tau = tau;
+                cs.h = h;
+                update_component(&g, q, F[q], &cs, F[cm->g1], F[cm->g2]);
             }
         }
     }

@@ -350,3 +350,19 @@ def test_curl_free_fields_rotate_by_exp_minus_i_omega_tau(oracle_lib, field):
             x2[2 * a] = comps[a]
         y2 = P(oracle.phi(coef, x2))
         assert np.linalg.norm(y2 - lam * P(x2)) > 1e-3 * np.linalg.norm(P(x2))
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 1)])
+def test_memory_light_mode_bitwise(oracle_lib, bcx, bcy):
+    """The memory-light iteration (coefficients evaluated per cell) equals the
+    stored-coefficient iteration bit for bit: all four sources, a graded PML,
+    back-iteration cells."""
+    pb = inputs.random_problem(7, 6, 12, seed=23, bcx=bcx, bcy=bcy)
+    g = inputs.rng(24)
+    mask = g.random(pb.shape) < 0.1
+    pb.eps[mask] = -g.uniform(1, 4, mask.sum()) + 1j * g.uniform(0.1, 1, mask.sum())
+    coef = _coef(pb)
+    a = oracle.iterate(coef, oracle.zero_fields(pb.shape), 9, bcx, bcy)
+    b = oracle.iterate_light(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h,
+                             oracle.zero_fields(pb.shape), 9, bcx, bcy)
+    assert np.array_equal(a, b)

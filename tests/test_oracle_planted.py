@@ -31,8 +31,8 @@ MUTATIONS = {
     # e^{-iwt/2} dropped from c_E
     "cE_phase": ("*c = (tau / (eps * h)) * conj(ph2) / d;", "*c = (tau / (eps * h)) / d;"),
     # real and imaginary parts of c swapped in the listing arithmetic
-    "swap_c": ("F[2 * p + 1] = fr * ti + fi * tr + srcq[2 * p + 1] - cr * Im - ci * Re;",
-               "F[2 * p + 1] = fr * ti + fi * tr + srcq[2 * p + 1] - ci * Im - cr * Re;"),
+    "swap_c": ("F[2 * p + 1] = fr * ti + fi * tr + si - cr * Im - ci * Re;",
+               "F[2 * p + 1] = fr * ti + fi * tr + si - ci * Im - cr * Re;"),
     # PML conductivity of H applied to the wrong components
     "pml_axis": ("double sst = (cq->axis == 2) ? sig_h[k] : 0.0;",
                  "double sst = (cq->axis == 1) ? sig_h[k] : 0.0;"),
