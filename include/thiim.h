@@ -208,13 +208,14 @@ typedef struct {
 } thiim_tuning;
 
 /* Picks the sweep configuration of thiim_iterate for this context: every
- * fused tile and blocked region crossed with z chunks from 16 planes to nz
- * is scored by a traffic / capacity model (HBM bytes per cell with tile
- * halos and z-chunk overlap, at a bandwidth share that drops when a launch
- * has fewer than 512 workgroups); the configurations within 1.3x of the best
- * score (at most 8) are timed over trial_iters iterations each, from the
- * current state into the spare buffer (the state does not advance), and the
- * fastest is kept.  All configurations give bit-identical iterates.
+ * fused tile and blocked region crossed with z chunks (16 planes to nz, and
+ * the round-quantisation choice of each geometry with its neighbours) is
+ * scored by a traffic / capacity model (HBM bytes per cell with tile halos
+ * and z-chunk overlap, stretched by the rounds of one-workgroup-per-CU that
+ * the launch needs); the configurations within 1.3x of the best score (at
+ * most 10) are timed over trial_iters iterations each, from the current
+ * state into the spare buffer (the state does not advance), and the fastest
+ * is kept.  All configurations give bit-identical iterates.
  * out may be NULL.  Synchronising. */
 int thiim_autotune(thiim_ctx *ctx, int trial_iters, thiim_tuning *out);
 

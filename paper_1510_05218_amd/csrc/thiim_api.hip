@@ -33,6 +33,13 @@ constexpr size_t kHeaderBytes = 4096;  // flag, reduction output
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Cells added to every array stride (17 x 256 bytes of complex128).  On a
+// power-of-two grid the arrays would otherwise all start at the same offset
+// modulo the HBM channel interleave, so the 25-52 streams of one sweep hit
+// the same channels together; an odd multiple of 256 bytes spreads them
+// (7-8% faster sweeps at 512^3).
+constexpr long long kStridePad = 272;
+
 struct Layout {
     long long N, S;   // cells, array stride (double2)
     size_t off_sig;   // 2*nz doubles
@@ -49,7 +56,7 @@ struct Layout {
 Layout layout_of(const thiim_grid* g) {
     Layout L;
     L.N = (long long)g->nx * g->ny * g->nz;
-    L.S = (long long)align_up((size_t)L.N, kAlign / 16);
+    L.S = (long long)align_up((size_t)L.N, kAlign / 16) + kStridePad;
     size_t off = kHeaderBytes;
     L.off_sig = off;
     off = align_up(off + 2 * sizeof(double) * g->nz, kAlign);
@@ -158,18 +165,44 @@ struct thiim_ctx {
     float4* ce32;                 // per-cell complex64 E-coefficient records
     thiim::PlaneCoef32* p32;      // per-plane complex64 H coefficients
     int inner_t, inner_rx, inner_ry, inner_chunk;
+    int ncu;          // compute units of the device
     double2* lam[4];  // adjoint buffers
     double2* gadj;    // adjoint source, 3 arrays
 };
 
 namespace {
 
-int auto_chunk(const thiim_grid& g, long long tiles) {
-    // enough workgroups to cover the 256 CUs several times over
-    int nch = (int)((2048 + tiles - 1) / tiles);
-    if (nch < 1) nch = 1;
-    int zc = (g.nz + nch - 1) / nch;
-    return zc < 32 ? 32 : zc;
+// Compute units of the current device (256 on an MI355X).
+int cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+        n = 256;
+    return n;
+}
+
+// z planes per workgroup stream.  The sweeps keep one workgroup resident per
+// CU (their LDS and registers allow no second), so a launch of W workgroups
+// runs in ceil(W / CUs) rounds, each about as long as one chunk plus ~3
+// planes of pipeline fill; choose the chunk count (chunks of >= 16 planes)
+// that minimises rounds x (chunk + 3).  At 512^3 the blocked sweep has 817
+// tiles and this picks 5 chunks of 103 planes; chunks of 86 to 171 planes
+// measure within a few per cent of each other there.
+int auto_chunk(const thiim_grid& g, long long tiles, int ncu) {
+    int best = 1;
+    double best_cost = INFINITY;
+    const int max_nch = g.nz / 16 > 1 ? g.nz / 16 : 1;
+    for (int nch = 1; nch <= max_nch; ++nch) {
+        const int zc = (g.nz + nch - 1) / nch;
+        const long long rounds = (tiles * nch + ncu - 1) / ncu;
+        const double cost = (double)rounds * (zc + 3);
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = nch;
+        }
+    }
+    return (g.nz + best - 1) / best;
 }
 
 int resolve_tiles(thiim_ctx* c) {
@@ -196,7 +229,7 @@ int resolve_tiles(thiim_ctx* c) {
     }
     const long long tiles = (long long)((g.nx + c->tile_x - 1) / c->tile_x) *
                             ((g.ny + c->tile_y - 1) / c->tile_y);
-    c->z_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, tiles);
+    c->z_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, tiles, c->ncu);
     c->t_block = g.t_block > 0 ? (g.t_block > 2 ? 2 : g.t_block) : 2;
     const bool btile = c->kernel == THIIM_KERNEL_BLOCKED && g.tile_x != 0;
     const bool compact = g.storage == THIIM_STORAGE_COMPACT;
@@ -204,14 +237,14 @@ int resolve_tiles(thiim_ctx* c) {
     c->region_y = btile ? g.tile_y : (compact ? 16 : 8);
     const int ox = c->region_x - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
     const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
-    c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles);
+    c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles, c->ncu);
     // complex64 inner sweeps of the mixed solver: region 32 x 16, T = 2 or 3
     c->inner_t = g.t_block >= 2 ? g.t_block : 2;
     c->inner_rx = 32;
     c->inner_ry = 16;
     const long long itiles = (long long)((g.nx + 32 - 2 * c->inner_t - 1) / (32 - 2 * c->inner_t)) *
                              ((g.ny + 16 - 2 * c->inner_t - 1) / (16 - 2 * c->inner_t));
-    c->inner_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, itiles);
+    c->inner_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, itiles, c->ncu);
     return THIIM_OK;
 }
 
@@ -289,6 +322,7 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->omega = omega;
     c->stream = (hipStream_t)g->stream;
     (void)hipGetDevice(&c->device);
+    c->ncu = cu_count();
     c->ws = (char*)workspace;
     c->flag = (int*)c->ws;
     c->out = (double*)(c->ws + 256);
@@ -714,10 +748,10 @@ struct Candidate {
 };
 
 // Modelled time of one iteration: HBM bytes per cell (tile halos and z-chunk
-// overlap included) over the bandwidth share of the workgroups that one
-// launch keeps resident (a launch with fewer workgroups than CUs leaves the
-// rest idle).
-double model_ms(const thiim_grid& g, const Candidate& c) {
+// overlap included) at 5 TB/s, stretched by the launch's round quantisation:
+// with one resident workgroup per CU, W workgroups of kchunk planes occupy
+// ceil(W / CUs) rounds of (kchunk + 3) plane-steps on every CU.
+double model_ms(const thiim_grid& g, const Candidate& c, int ncu) {
     const double N = (double)g.nx * g.ny * g.nz;
     const bool compact = g.storage == THIIM_STORAGE_COMPACT;
     const double reads = compact ? 13.0 : 36.0;  // arrays read per cell and pass
@@ -738,8 +772,9 @@ double model_ms(const thiim_grid& g, const Candidate& c) {
         wgs = (double)((g.nx + c.tx - 1) / c.tx) * ((g.ny + c.ty - 1) / c.ty) *
               ((g.nz + c.chunk - 1) / c.chunk);
     }
-    const double fill = wgs >= 512.0 ? 1.0 : wgs / 512.0;
-    return bytes * N / (5.0e12 * fill) * 1e3;
+    const double rounds = std::ceil(wgs / ncu);
+    const double quant = rounds * ncu * (c.chunk + 3.0) / (wgs * c.chunk);
+    return bytes * N / 5.0e12 * quant * 1e3;
 }
 
 void apply(thiim_ctx* c, const Candidate& k) {
@@ -776,8 +811,17 @@ int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
     const thiim_grid& g = c->g;
     std::vector<Candidate> all;
     std::vector<int> chunks = {16, 32, 64, 128, 256, g.nz};
-    chunks.push_back(auto_chunk(g, ((g.nx + 27) / 28) * ((g.ny + 11) / 12)));
+    // the round-quantisation choice for each sweep geometry, and its neighbours
+    for (long long tl : {(long long)((g.nx + 27) / 28) * ((g.ny + 11) / 12),
+                         (long long)((g.nx + 59) / 60) * ((g.ny + 3) / 4),
+                         (long long)((g.nx + 63) / 64) * ((g.ny + 7) / 8)}) {
+        const int zc = auto_chunk(g, tl, c->ncu);
+        const int nch = (g.nz + zc - 1) / zc;
+        for (int d = -1; d <= 1; ++d)
+            if (nch + d >= 1) chunks.push_back((g.nz + nch + d - 1) / (nch + d));
+    }
     chunks.push_back(c->z_chunk);
+    chunks.push_back(c->bz_chunk);
     std::sort(chunks.begin(), chunks.end());
     chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
     const int regions[3][2] = {{32, 16}, {64, 8}, {64, 6}};
@@ -787,13 +831,13 @@ int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
         for (auto& r : regions) all.push_back({THIIM_KERNEL_BLOCKED, r[0], r[1], zc, 0.0});
         for (auto& t : tiles) all.push_back({THIIM_KERNEL_FUSED, t[0], t[1], zc, 0.0});
     }
-    for (auto& k : all) k.model_ms = model_ms(g, k);
+    for (auto& k : all) k.model_ms = model_ms(g, k, c->ncu);
     std::sort(all.begin(), all.end(),
               [](const Candidate& a, const Candidate& b) { return a.model_ms < b.model_ms; });
     const double cut = 1.3 * all.front().model_ms;
     std::vector<Candidate> keep;
     for (auto& k : all)
-        if (k.model_ms <= cut && keep.size() < 8) keep.push_back(k);
+        if (k.model_ms <= cut && keep.size() < 10) keep.push_back(k);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(THIIM_EDEVICE, "autotune: event create");
@@ -1344,7 +1388,7 @@ int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
             const int ox = k.kernel == THIIM_KERNEL_BLOCKED ? k.tx - 4 : k.tx;
             const int oy = k.kernel == THIIM_KERNEL_BLOCKED ? k.ty - 4 : k.ty;
             const long long tiles = (long long)((c->g.nx + ox - 1) / ox) * ((c->g.ny + oy - 1) / oy);
-            int zc = k.chunk > 0 ? std::min(k.chunk, c->g.nz) : auto_chunk(c->g, tiles);
+            int zc = k.chunk > 0 ? std::min(k.chunk, c->g.nz) : auto_chunk(c->g, tiles, c->ncu);
             apply(c, Candidate{k.kernel, k.tx, k.ty, zc, 0.0});
         }
         b->dirty = true;

@@ -55,7 +55,8 @@ def test_adjoint_workspace():
     ga = thiim.make_grid((36, 24, 24), storage="compact", adjoint=True)
     n = 24 * 24 * 36
     extra = thiim.thiim_workspace_bytes(ga) - thiim.thiim_workspace_bytes(g)
-    assert abs(extra - 51 * 16 * n) < 2 ** 12  # 4 x 12 adjoint buffers + 3 source arrays
+    # 4 x 12 adjoint buffers + 3 source arrays, each of a padded stride
+    assert 51 * 16 * n <= extra < 51 * 16 * (n + 1024)
     with pytest.raises(thiim.ThiimError) as e:
         thiim.thiim_workspace_bytes(thiim.make_grid((8, 8, 8), storage="full", adjoint=True))
     assert e.value.status == thiim.THIIM_EINVAL
