@@ -165,7 +165,7 @@ def adjoint_context(torch, thiim, pb, n_cells, w):
         del grad
     s.close()
     ms = (times[30] - times[10]) / 20 * 1e3
-    return {"ms_per_iteration": ms, "sweep_kernel": "k_adjoint<64,8,CompactCoefs>",
+    return {"ms_per_iteration": ms, "sweep_kernel": "k_adjoint<64,8,AdjPol64<false>>",
             "sweep_glups": n_cells / (ms * 1e-3) / 1e9,
             "alg_bytes_per_lup": ADJ_BYTES_PER_LUP,
             "alg_gbs": ADJ_BYTES_PER_LUP * n_cells / (ms * 1e-3) / 1e9}

@@ -50,7 +50,12 @@ ALG_BYTES_PER_CELL = {
     "k_blocked<32,16,2,Pol64<CompactCoefs>>": 400,
     "k_blocked<64,8,2,Pol64<CompactCoefs>>": 400,
     # transposed sweep: 12 lam + eps + 3 g read, 12 written
-    "k_adjoint<64,8,CompactCoefs>": 448,
+    "k_adjoint<64,8,AdjPol64<false>>": 448,
+    # with a source on every part (defect correction): 12 lam + eps + 12 G
+    "k_adjoint<64,8,AdjPol64<true>>": 592,
+    # complex64 transposed inner sweep: 12 lam + 16 B record + 12 G read,
+    # 12 lam written
+    "k_adjoint<64,8,AdjPol32>": 304,
     # complex64 inner sweeps (8 B per value): 12 d + 12 r + 16 B record read,
     # 12 d written
     "k_blocked<32,16,2,Pol32>": 304,
