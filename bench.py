@@ -27,10 +27,22 @@ a 128 x 128 x 256 grid of the same generator, and a batched spectral sweep
 (4 wavelengths x 2 geometries: batched against one-by-one throughput, and
 the batched mixed solver against plain FP64 solves in solves/s).
 
+The roofline entry also carries the bandwidth of a plain 4 GiB device copy
+measured in the same process (``copy_gbs``) and the sweep's fractions of it,
+the counter bandwidth when ``traffic`` is known, and the GLUP/s over the
+roofline of the naive sweep on the paper's layout (8 TB/s / 1024 B per
+lattice update), which temporal blocking can exceed.
+
+``--oracle-timing`` instead times the CPU oracle alone (no GPU use) on the
+sizes of the measurement plan -- 24 x 24 x 36 for 200 iterations, 128^3 for
+20, 256^3 for 10 and 512^3 in the memory-light mode for 5 -- one warm-up run
+and the median of three, on all host threads and, for the two small grids,
+on one thread, and prints one JSON line.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 512]
        [--iters 100] [--kernel blocked] [--storage compact] [--no-cpu-baseline]
        [--no-context] [--no-adjoint] [--no-solve] [--solve-grid 128x128x256]
-       [--no-spectral]
+       [--no-spectral] [--oracle-timing]
 """
 import argparse
 import json
@@ -148,6 +160,93 @@ def cpu_baseline(pb_full, budget_s=15.0):
                   f"(28-array layout, C, OpenMP), {n} iterations in {dt:.1f} s",
         "single_core_value": eps.size * n1 / dt1 / 1e9,
     }
+
+
+def oracle_timing():
+    """The CPU oracle on the measurement plan's sizes: one warm-up run, then
+    the median of three timed runs (MLUP/s), all host threads; one thread as
+    well on the two small grids."""
+    import platform
+    import statistics
+
+    import oracle
+    from paper_1510_05218_amd import inputs
+
+    def model():
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+        except OSError:
+            pass
+        return platform.processor()
+
+    def timed(run, n_lup):
+        run()
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            run()
+            ts.append(time.perf_counter() - t)
+        med = statistics.median(ts)
+        return {"seconds": med, "mlups": n_lup / med / 1e6}
+
+    cases = [("24x24x36", (36, 24, 24), 1, 200, False, True),
+             ("128^3", (128, 128, 128), 3, 20, False, True),
+             ("256^3", (256, 256, 256), 3, 10, False, False),
+             ("512^3 memory-light", (512, 512, 512), 3, 5, True, False)]
+    cores = oracle.num_threads()
+    out = {"kind": "oracle", "cpu": model(), "threads": cores, "cases": {}}
+    for name, shape, seed, its, light, single in cases:
+        nz, ny, nx = shape
+        log(f"[oracle timing] {name}: {its} iterations")
+        pb = inputs.solar_cell(nx, ny, nz, seed=seed, npml=6,
+                               n_spheres=200 if nx >= 512 else 0)
+        n_lup = nx * ny * nz * its
+        if light:
+            x = oracle.zero_fields(shape)
+
+            def run():
+                oracle.iterate_light(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega,
+                                     pb.tau, pb.h, x, its)
+        else:
+            coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau)
+            x = oracle.zero_fields(shape)
+
+            def run():
+                oracle.iterate(coef, x, its)
+        case = {"iterations": its, "all_threads": timed(run, n_lup)}
+        if single:
+            oracle.set_threads(1)
+            case["one_thread"] = timed(run, n_lup)
+            oracle.set_threads(cores)
+        out["cases"][name] = case
+        log(f"[oracle timing] {name}: {case['all_threads']['mlups']:.1f} MLUP/s")
+        del x
+        if not light:
+            del coef
+    return out
+
+
+def copy_bandwidth(torch):
+    """A plain 4 GiB device-to-device copy (torch's copy kernel): median of
+    five, GB/s counting the bytes read and written."""
+    a = torch.empty(2 ** 32, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    ts.sort()
+    return 2 * 2 ** 32 / (ts[2] * 1e-3) / 1e9
 
 
 def adjoint_context(torch, thiim, pb, n_cells, w):
@@ -303,7 +402,13 @@ def main():
                     help="skip the batched spectral-sweep comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (counter calibration)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the CPU oracle on the measurement plan's sizes only")
     args = ap.parse_args()
+
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py: this THIIM build runs on one GPU only; the z-slab multi-GPU "
@@ -354,6 +459,8 @@ def main():
     bytes_per_launch = BYTES_PER_LUP[head] * N * ipl
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     traffic = traffic_for(SWEEP_KERNEL[head], N)
+    copy_gbs = copy_bandwidth(torch)
+    log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
     kernels = {}
     for (k, st), (sm, im, r) in results.items():
         ms = sum(im) / len(im)
@@ -402,7 +509,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL[head], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "alg_bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms},
+                     "alg_bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "counter_gbs": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+                     "counter_frac": None if traffic is None
+                     else traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "counter_frac_of_copy": None if traffic is None
+                     else traffic / (launch_ms * 1e-3) / 1e9 / copy_gbs,
+                     "glups_over_naive_roofline": N / (it_ms * 1e-3) / 1e9
+                     / (HBM_PEAK_GBS / 1024.0)},
         "cpu_baseline": cpu,
         "kernels": kernels,
         "solve_1e-8": solve,

@@ -90,8 +90,9 @@ typedef struct {
     int kernel;       /* THIIM_KERNEL_* */
     int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED: 0 (auto,
                        * = 2), 1 or 2; a remainder runs through the fused sweep.
-                       * With THIIM_PRECISION_MIXED, 3 is also allowed and then
-                       * applies to the complex64 inner sweeps only */
+                       * With THIIM_PRECISION_MIXED, 3 is also allowed; the
+                       * complex64 inner sweeps run 3 iterations per pass for
+                       * 0 (auto) and 3, and 2 for 1 and 2 */
     int tile_x, tile_y; /* fused sweep: tile 64x8, 32x8, 64x4 or 16x16; blocked
                          * sweep: region 64x8, 64x6 or 32x16 (columns x rows) of
                          * which the centre (x-2T) x (y-2T) is stored; 0x0 = auto */

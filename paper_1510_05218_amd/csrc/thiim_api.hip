@@ -238,8 +238,9 @@ int resolve_tiles(thiim_ctx* c) {
     const int ox = c->region_x - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
     const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
     c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles, c->ncu);
-    // complex64 inner sweeps of the mixed solver: region 32 x 16, T = 2 or 3
-    c->inner_t = g.t_block >= 2 ? g.t_block : 2;
+    // complex64 inner sweeps of the mixed solver: region 32 x 16, T = 3 unless
+    // 1 or 2 is asked for (T = 3: 101 B per lattice update against 152)
+    c->inner_t = g.t_block == 1 || g.t_block == 2 ? 2 : 3;
     c->inner_rx = 32;
     c->inner_ry = 16;
     const long long itiles = (long long)((g.nx + 32 - 2 * c->inner_t - 1) / (32 - 2 * c->inner_t)) *

@@ -212,29 +212,29 @@ __device__ __forceinline__ PlaneCoef plane_coef(double sig_h, double sig_e, cons
 struct ECoef {
     double2 t0, t1, c0, c1, s1;
 };
+// With a = |eps'| and d_j = a + tau sigma_j (sigma_0 = w eps'', sigma_1 =
+// sigma_0 + sigma_e) both branches above become
+//   t_j = (a / d_j) e^{-+iwt},  c_j = (tau/h) / d_j e^{-+iwt/2},
+//   Src scale = tau a / d_j e^{-iwt} (eps' > 0) or -tau a / d_j (eps' < 0),
+// upper signs for eps' > 0; 1/d_0 and 1/d_1 come from one division,
+// 1/(d_0 d_1).  (The sweeps evaluate this for every E cell of every stage.)
 __device__ __forceinline__ ECoef cell_e(double2 eps, double sig_e, const CoefConst& K) {
-    const double inv = 1.0 / eps.x;
-    const double cs = K.tau * inv / K.h;  // tau / (eps' h)
+    const bool pos = eps.x > 0.0;
+    const double a = fabs(eps.x);
     const double sg0 = K.omega * eps.y;
-    const double sg1 = sg0 + sig_e;
+    const double d0 = a + K.tau * sg0;
+    const double d1 = d0 + K.tau * sig_e;
+    const double p = 1.0 / (d0 * d1);
+    const double q0 = d1 * p, q1 = d0 * p;
+    const double2 ph = pos ? K.phc : K.ph;
+    const double2 ph2 = pos ? K.ph2c : K.ph2;
+    const double th = K.tau / K.h;
     ECoef r;
-    if (eps.x > 0.0) {
-        const double r0 = 1.0 / (1.0 + K.tau * sg0 * inv);
-        const double r1 = 1.0 / (1.0 + K.tau * sg1 * inv);
-        r.t0 = cscale(r0, K.phc);
-        r.t1 = cscale(r1, K.phc);
-        r.c0 = cscale(cs * r0, K.ph2c);
-        r.c1 = cscale(cs * r1, K.ph2c);
-        r.s1 = cscale(K.tau * r1, K.phc);
-    } else {
-        const double r0 = 1.0 / (1.0 - K.tau * sg0 * inv);
-        const double r1 = 1.0 / (1.0 - K.tau * sg1 * inv);
-        r.t0 = cscale(r0, K.ph);
-        r.t1 = cscale(r1, K.ph);
-        r.c0 = cscale(-cs * r0, K.ph2);
-        r.c1 = cscale(-cs * r1, K.ph2);
-        r.s1 = make_double2(-K.tau * r1, 0.0);
-    }
+    r.t0 = cscale(a * q0, ph);
+    r.t1 = cscale(a * q1, ph);
+    r.c0 = cscale(th * q0, ph2);
+    r.c1 = cscale(th * q1, ph2);
+    r.s1 = pos ? cscale(K.tau * a * q1, K.phc) : make_double2(-K.tau * a * q1, 0.0);
     return r;
 }
 
