@@ -118,6 +118,35 @@ def test_tiny_grids_wrap_many_times():
         assert torch.equal(xbc, xn)
 
 
+def test_smallest_grid_and_zero_iterations():
+    """Degenerate cases: the smallest legal grid (2 x 2 x 2: every cell is a
+    boundary cell on all three axes; periodic and Dirichlet x/y, back-
+    iteration cells included) on every kernel and storage, and zero
+    iterations, which leave the fields bit for bit as they were (zero at
+    create, the current iterate later)."""
+    _require_gpu()
+    for bcx, bcy in [(0, 0), (1, 1)]:
+        pb = inputs.random_problem(2, 2, 2, seed=5, npml=0, bcx=bcx, bcy=bcy)
+        pb.eps[0, 1, 0] = -2.5 + 0.3j
+        _, xo = _oracle_run(pb, 30)
+        assert np.linalg.norm(xo) > 0
+        for kernel in ("naive", "fused", "blocked"):
+            for storage in ("full", "compact"):
+                s, xg = _gpu_run(pb, 30, kernel=kernel, storage=storage)
+                s.close()
+                assert _rel(xg.cpu().numpy(), xo) < 1e-12, (bcx, kernel, storage)
+    pb = inputs.solar_cell(24, 24, 36, seed=1, npml=6)
+    s = thiim.Solver(pb, kernel="blocked", storage="compact")
+    s.iterate(0)
+    assert not torch.any(s.fields() != 0)
+    s.iterate(7)
+    x7 = s.fields().clone()
+    s.iterate(0)
+    assert torch.equal(s.fields(), x7)
+    assert s.iterations == 7
+    s.close()
+
+
 def test_zero_source_stays_zero():
     _require_gpu()
     pb = inputs.solar_cell(24, 20, 30, seed=2, npml=4)
