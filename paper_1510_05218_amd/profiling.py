@@ -13,6 +13,8 @@
   benchmark problem, with T = 2 and with T = 3 inner passes.
 * ``run_solve``: time to relative residual 1e-8 on the n^3 benchmark
   problem, mixed solver against the plain FP64 iteration.
+* ``run_c3``: the mixed solver on the n^3 benchmark problem to 1e-8 and on
+  to 1e-10; the error of the 1e-8 solution against the 1e-10 one.
 * ``run_spectral``: the full batched spectral sweep (32 wavelengths x 4
   geometries up to 192 x 192 x 384) to 1e-8 in resident waves.
 
@@ -21,6 +23,7 @@ Usage:
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
+    python -m paper_1510_05218_amd.profiling run_c3 [n]
     python -m paper_1510_05218_amd.profiling run_spectral [waves]
 """
 from __future__ import annotations
@@ -223,6 +226,48 @@ def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
     print(json.dumps(out), flush=True)
 
 
+def run_c3(n=512, tol=1e-8, ref_tol=1e-10, m=2000):
+    """The mixed solver (T = 3, m inner sweeps per correction) on the n^3
+    benchmark workload to tol, then the same context on to ref_tol: the
+    second iterate is the FP64 fixed point to ref_tol (its residual is the
+    FP64 one), and the relative 2-norm difference of the physical fields is
+    the error of the tol solution.  Slices of three corrections print their
+    progress."""
+    import time
+
+    import torch
+
+    from . import inputs, thiim
+
+    pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200 if n >= 128 else 0)
+    dev = inputs.Problem(**{**pb.__dict__})
+    dev.eps = torch.from_numpy(pb.eps).cuda()
+    dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
+    out = {"grid": f"{n}^3", "tol": tol, "ref_tol": ref_tol, "inner_sweeps": m}
+    s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=3)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    sweeps, r, snap = 0, 1.0, None
+    for goal in (tol, ref_tol):
+        while r > goal and sweeps < 1000000:
+            rc, it, r = s.solve(goal, 3 * (m + 1), m)
+            sweeps += it
+            print(json.dumps({"sweeps": sweeps, "rel_res": r, "s": round(time.time() - t0, 1)}),
+                  flush=True)
+        out[f"to_{goal:g}"] = {"sweeps": sweeps, "rel_res": r, "seconds": time.time() - t0}
+        x = s.fields()
+        p = x[0::2] + x[1::2]
+        del x
+        if snap is None:
+            snap = p
+        else:
+            out["error_vs_ref"] = float(torch.linalg.vector_norm(snap - p) /
+                                        torch.linalg.vector_norm(p))
+        torch.cuda.empty_cache()
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 SPECTRAL_GEOMETRIES = [(64, 64, 64, 10), (96, 96, 128, 11), (128, 128, 256, 12),
                        (192, 192, 384, 13)]
 
@@ -286,6 +331,8 @@ def main(argv):
         run_mixed(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_solve":
         run_solve_512(int(argv[1]) if len(argv) > 1 else 512)
+    elif argv[0] == "run_c3":
+        run_c3(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_spectral":
         run_spectral(argv[1] if len(argv) > 1 else "0,1,2:3a:3b:3c")
     else:
