@@ -28,9 +28,15 @@ struct PlaneCoef {
 };
 
 // H coefficients of one plane rounded to complex64 (inner sweeps of the
-// mixed-precision solver).
+// mixed-precision solver), and which split pairs of the plane have two parts
+// with identical coefficients: on such a plane the defect step stores the
+// same value for both parts of the pair in r (k_defect_partial), and the
+// inner sweeps read it once.
 struct PlaneCoef32 {
     float2 th0, thz, ch0, chz;
+    int hsym;    // the x and y pairs of H (the z pair always)
+    int esym;    // the x and y pairs of E (the z pair always)
+    int pad[2];
 };
 
 // Where the sweeps find their coefficients.

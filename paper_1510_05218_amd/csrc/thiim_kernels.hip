@@ -212,6 +212,16 @@ __device__ __forceinline__ PlaneCoef plane_coef(double sig_h, double sig_e, cons
     return pc;
 }
 
+// Split pairs c = 0..5 (H_x, H_y, H_z, E_x, E_y, E_z) whose two parts have
+// identical coefficients on a plane: the z pairs everywhere, the x and y
+// pairs where the plane carries no PML term.
+__host__ __device__ __forceinline__ bool h_pairs_sym(const PlaneCoef& pc) {
+    return pc.thz.x == pc.th0.x && pc.thz.y == pc.th0.y;
+}
+__host__ __device__ __forceinline__ bool e_pairs_sym(const PlaneCoef& pc) {
+    return pc.sig_e == 0.0;
+}
+
 // E coefficients of one cell: index 0 = parts with an x/y difference,
 // 1 = parts with a z difference (PML term sig_e added); s1 = Src scale.
 struct ECoef {
@@ -466,13 +476,30 @@ struct Pol32 {
     const float2* __restrict__ r;        // 12 arrays, stride S
     long long S;
     float2 ph, phc, ph2, ph2c;
-    __device__ __forceinline__ void load_h_src(long long po, uint32_t bo, V src[6]) const {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) src[q] = ldo(r + q * S + po, bo);
+    // r of the six H (E) parts of plane k; where the defect step stored one
+    // value for both parts of a pair (PlaneCoef32::hsym / esym, the z pair
+    // always) it is read once: 6 instead of 12 reads per cell off the PML
+    __device__ __forceinline__ void load_pairs(const float2* __restrict__ rr, bool sym,
+                                               long long po, uint32_t bo, V src[6]) const {
+        src[0] = ldo(rr + 0 * S + po, bo);
+        src[2] = ldo(rr + 2 * S + po, bo);
+        src[4] = ldo(rr + 4 * S + po, bo);
+        src[5] = src[4];
+        if (sym) {
+            src[1] = src[0];
+            src[3] = src[2];
+        } else {
+            src[1] = ldo(rr + 1 * S + po, bo);
+            src[3] = ldo(rr + 3 * S + po, bo);
+        }
     }
-    __device__ __forceinline__ void load_e_src(long long po, uint32_t bo, V src[6]) const {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) src[q] = ldo(r + (6 + q) * S + po, bo);
+    __device__ __forceinline__ void load_h_src(int k, long long po, uint32_t bo,
+                                               V src[6]) const {
+        load_pairs(r, P32[k].hsym != 0, po, bo, src);
+    }
+    __device__ __forceinline__ void load_e_src(int k, long long po, uint32_t bo,
+                                               V src[6]) const {
+        load_pairs(r + 6 * S, P32[k].esym != 0, po, bo, src);
     }
     __device__ __forceinline__ CRec load_crec(long long po, uint32_t bo) const {
         return ldo(ce + po, bo);
@@ -537,6 +564,9 @@ __global__ void k_prep32(CompactCoefs cp, Geo g, float4* __restrict__ ce,
             q.thz = to32(pc.thz);
             q.ch0 = to32(pc.ch0);
             q.chz = to32(pc.chz);
+            q.hsym = h_pairs_sym(pc) ? 1 : 0;
+            q.esym = e_pairs_sym(pc) ? 1 : 0;
+            q.pad[0] = q.pad[1] = 0;
             P32[p] = q;
         }
     }
@@ -980,8 +1010,9 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
         if constexpr (P::CARRY) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) rHq[0][q] = rEq[0][q] = vzero<V>();
-            if (valid && k < g.nz) pol.load_h_src(k * plane, bo, rHq[0]);
-            if (valid && k >= 1 && k - 1 < g.nz) pol.load_e_src((k - 1) * plane, bo, rEq[0]);
+            if (valid && k < g.nz) pol.load_h_src(k, k * plane, bo, rHq[0]);
+            if (valid && k >= 1 && k - 1 < g.nz)
+                pol.load_e_src(k - 1, (k - 1) * plane, bo, rEq[0]);
         }
         if constexpr (P::CARRY_REC) {
             if (valid && k >= 1 && k - 1 < g.nz) crq[0] = pol.load_crec((k - 1) * plane, bo);
@@ -1691,8 +1722,8 @@ __global__ __launch_bounds__(256) void k_defect_partial(const double2* __restric
          p += stride) {
         const int k = (int)(p / nxy);
         const PlaneCoef pc = P[k];
-        const bool hsym = pc.thz.x == pc.th0.x && pc.thz.y == pc.th0.y;
-        const bool esym = pc.sig_e == 0.0;
+        const bool hsym = h_pairs_sym(pc);
+        const bool esym = e_pairs_sym(pc);
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             const double2 a0 = A[(2 * c) * S + p], a1 = A[(2 * c + 1) * S + p];
