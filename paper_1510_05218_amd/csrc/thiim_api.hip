@@ -530,7 +530,8 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
                                       c->inner_chunk, c->stream);
             di = 1 - di;
             if (e == hipSuccess && p >= passes - Kp)
-                e = thiim::launch_accum(c->F[c->cur], c->d32[di], 1.0 / Kp, c->L.S, c->L.N,
+                e = thiim::launch_accum(c->F[c->cur], c->d32[di], 1.0 / Kp, c->cv.P,
+                                        (long long)c->g.nx * c->g.ny, c->L.S, c->L.N,
                                         c->stream);
         }
         if (e != hipSuccess) return hip_fail(e, "mixed: inner sweeps");
@@ -668,7 +669,8 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
                                                 c->tile_y, c->z_chunk, c->stream);
                     di = 1 - di;
                     if (e == hipSuccess && p >= m - Kp)
-                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kp, S, N, c->stream);
+                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kp, nullptr, 0, S,
+                                                N, c->stream);
                 }
             } else {
                 if (e == hipSuccess)
@@ -1223,6 +1225,7 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                         if (err != hipSuccess || p < P - Kp[i]) continue;
                         thiim_ctx* c = b->ctx[i];
                         err = thiim::launch_accum(c->F[c->cur], c->d32[(p + 1) & 1], 1.0 / Kp[i],
+                                                  c->cv.P, (long long)c->g.nx * c->g.ny,
                                                   c->L.S, c->L.N, b->stream);
                     }
                 }

@@ -422,6 +422,23 @@ struct Pol64 {
         if constexpr (CP::COMPACT) return ldo(cp.eps + po, bo);
         else return CRec{};
     }
+    // the six H or E parts of a plane, as stored
+    __device__ __forceinline__ void load_h(const V* F, long long S, int, long long po,
+                                           uint32_t bo, V v[6]) const {
+        load6v(F, S, po, bo, v);
+    }
+    __device__ __forceinline__ void load_e(const V* F, long long S, int, long long po,
+                                           uint32_t bo, V v[6]) const {
+        load6v(F, S, po, bo, v);
+    }
+    __device__ __forceinline__ void store_h(V* F, long long S, int, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        store6v(F, S, po, bo, v);
+    }
+    __device__ __forceinline__ void store_e(V* F, long long S, int, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        store6v(F, S, po, bo, v);
+    }
     __device__ __forceinline__ void ecoef_rec(int k, CRec eps_k, long long po, uint32_t bo,
                                               V t[6], V c[6], V src[6]) const {
         if constexpr (CP::COMPACT) {
@@ -476,22 +493,37 @@ struct Pol32 {
     const float2* __restrict__ r;        // 12 arrays, stride S
     long long S;
     float2 ph, phc, ph2, ph2c;
-    // r of the six H (E) parts of plane k; where the defect step stored one
-    // value for both parts of a pair (PlaneCoef32::hsym / esym, the z pair
-    // always) it is read once: 6 instead of 12 reads per cell off the PML
-    __device__ __forceinline__ void load_pairs(const float2* __restrict__ rr, bool sym,
-                                               long long po, uint32_t bo, V src[6]) const {
-        src[0] = ldo(rr + 0 * S + po, bo);
-        src[2] = ldo(rr + 2 * S + po, bo);
-        src[4] = ldo(rr + 4 * S + po, bo);
-        src[5] = src[4];
+    // Pair-sum form.  Where both parts of a split pair have identical
+    // coefficients (PlaneCoef32::hsym / esym for the x and y pairs, always for
+    // the z pairs) one pass maps the pair's sum to t * sum + (both parts'
+    // increments), whatever the split: such a pair is kept as (sum, 0), of
+    // which only the first part is read and written (r the same, as the
+    // defect step stores it).  Off the PML that halves the d and r traffic.
+    __device__ __forceinline__ void load_pairs(const V* __restrict__ F, bool sym, long long po,
+                                               uint32_t bo, V v[6]) const {
+        v[0] = ldo(F + 0 * S + po, bo);
+        v[2] = ldo(F + 2 * S + po, bo);
+        v[4] = ldo(F + 4 * S + po, bo);
+        v[5] = make_float2(0.0f, 0.0f);
         if (sym) {
-            src[1] = src[0];
-            src[3] = src[2];
+            v[1] = v[3] = make_float2(0.0f, 0.0f);
         } else {
-            src[1] = ldo(rr + 1 * S + po, bo);
-            src[3] = ldo(rr + 3 * S + po, bo);
+            v[1] = ldo(F + 1 * S + po, bo);
+            v[3] = ldo(F + 3 * S + po, bo);
         }
+    }
+    __device__ __forceinline__ void store_pairs(V* __restrict__ F, bool sym, long long po,
+                                                uint32_t bo, const V v[6]) const {
+        if (sym) {
+            sto(F + 0 * S + po, bo, cadd(v[0], v[1]));
+            sto(F + 2 * S + po, bo, cadd(v[2], v[3]));
+        } else {
+            sto(F + 0 * S + po, bo, v[0]);
+            sto(F + 1 * S + po, bo, v[1]);
+            sto(F + 2 * S + po, bo, v[2]);
+            sto(F + 3 * S + po, bo, v[3]);
+        }
+        sto(F + 4 * S + po, bo, cadd(v[4], v[5]));
     }
     __device__ __forceinline__ void load_h_src(int k, long long po, uint32_t bo,
                                                V src[6]) const {
@@ -500,6 +532,22 @@ struct Pol32 {
     __device__ __forceinline__ void load_e_src(int k, long long po, uint32_t bo,
                                                V src[6]) const {
         load_pairs(r + 6 * S, P32[k].esym != 0, po, bo, src);
+    }
+    __device__ __forceinline__ void load_h(const V* F, long long, int k, long long po,
+                                           uint32_t bo, V v[6]) const {
+        load_pairs(F, P32[k].hsym != 0, po, bo, v);
+    }
+    __device__ __forceinline__ void load_e(const V* F, long long, int k, long long po,
+                                           uint32_t bo, V v[6]) const {
+        load_pairs(F, P32[k].esym != 0, po, bo, v);
+    }
+    __device__ __forceinline__ void store_h(V* F, long long, int k, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        store_pairs(F, P32[k].hsym != 0, po, bo, v);
+    }
+    __device__ __forceinline__ void store_e(V* F, long long, int k, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        store_pairs(F, P32[k].esym != 0, po, bo, v);
     }
     __device__ __forceinline__ CRec load_crec(long long po, uint32_t bo) const {
         return ldo(ce + po, bo);
@@ -992,7 +1040,7 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
             if (q < 3) hcs[s][q] = vzero<V>();
         }
     }
-    if (ks > 0 && valid) load6v(AE, S, (ks - 1) * plane, bo, e0p);
+    if (ks > 0 && valid) pol.load_e(AE, S, ks - 1, (ks - 1) * plane, bo, e0p);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
@@ -1004,8 +1052,8 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
 #pragma unroll
         for (int q = 0; q < 6; ++q) e0c[q] = h0c[q] = vzero<V>();
         if (k < g.nz && valid) {
-            load6v(AE, S, k * plane, bo, e0c);
-            load6v(A, S, k * plane, bo, h0c);
+            pol.load_e(AE, S, k, k * plane, bo, e0c);
+            pol.load_h(A, S, k, k * plane, bo, h0c);
         }
         if constexpr (P::CARRY) {
 #pragma unroll
@@ -1068,7 +1116,7 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = cadd(h[q], src[q]);
                 }
-                if (s == T && own && kh >= k0 && kh < k1) store6v(B, S, po, bo, h);
+                if (s == T && own && kh >= k0 && kh < k1) pol.store_h(B, S, kh, po, bo, h);
             }
             const V hx = hsum[0], hy = hsum[1], hz = hsum[2];
             LH[s - 1][par][0][me] = hx;
@@ -1119,7 +1167,7 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                     pol.ecoef(ke, po, bo, t, c, src);
                 }
                 update_e_t<P::EMASK>(e, t, c, src, nb);
-                if (s == T && own && ke >= k0 && ke < k1) store6v(BE, S, po, bo, e);
+                if (s == T && own && ke >= k0 && ke < k1) pol.store_e(BE, S, ke, po, bo, e);
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) en[s - 1][q] = e[q];
@@ -1732,9 +1780,8 @@ __global__ __launch_bounds__(256) void k_defect_partial(const double2* __restric
             const double2 d = cadd(d0, d1);
             const bool sym = (c == 2 || c == 5) || (c < 3 ? hsym : esym);
             if (sym) {
-                const float2 m = make_float2((float)(0.5 * d.x), (float)(0.5 * d.y));
-                R[(2 * c) * S + p] = m;
-                R[(2 * c + 1) * S + p] = m;
+                R[(2 * c) * S + p] = make_float2((float)d.x, (float)d.y);
+                R[(2 * c + 1) * S + p] = make_float2(0.0f, 0.0f);
             } else {
                 R[(2 * c) * S + p] = make_float2((float)d0.x, (float)d0.y);
                 R[(2 * c + 1) * S + p] = make_float2((float)d1.x, (float)d1.y);
@@ -1754,16 +1801,39 @@ __global__ __launch_bounds__(256) void k_defect_partial(const double2* __restric
     }
 }
 
-// x += w d (complex64 correction accumulated in FP64), all 12 arrays.
+// x += w d (complex64 correction accumulated in FP64), all 12 arrays.  With
+// a plane table P, d is in the pair-sum form of the complex64 inner sweeps
+// (a symmetric pair is (sum, 0), its second part not stored) and each part
+// of such a pair receives w sum / 2; without, d holds all 12 parts.
 __global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, double w,
-                        long long S, long long N) {
+                        const PlaneCoef* __restrict__ P, long long nxy, long long S,
+                        long long N) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+        bool hsym = false, esym = false;
+        if (P) {
+            const PlaneCoef pc = P[p / nxy];
+            hsym = h_pairs_sym(pc);
+            esym = e_pairs_sym(pc);
+        }
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const double2 x = X[q * S + p];
-            const float2 d = D[q * S + p];
-            X[q * S + p] = make_double2(__fma_rn(w, (double)d.x, x.x), __fma_rn(w, (double)d.y, x.y));
+        for (int c = 0; c < 6; ++c) {
+            const bool sym = P && ((c == 2 || c == 5) || (c < 3 ? hsym : esym));
+            const double2 x0 = X[(2 * c) * S + p], x1 = X[(2 * c + 1) * S + p];
+            const float2 d0 = D[(2 * c) * S + p];
+            if (sym) {
+                const double hw = 0.5 * w;
+                X[(2 * c) * S + p] = make_double2(__fma_rn(hw, (double)d0.x, x0.x),
+                                                  __fma_rn(hw, (double)d0.y, x0.y));
+                X[(2 * c + 1) * S + p] = make_double2(__fma_rn(hw, (double)d0.x, x1.x),
+                                                      __fma_rn(hw, (double)d0.y, x1.y));
+            } else {
+                const float2 d1 = D[(2 * c + 1) * S + p];
+                X[(2 * c) * S + p] = make_double2(__fma_rn(w, (double)d0.x, x0.x),
+                                                  __fma_rn(w, (double)d0.y, x0.y));
+                X[(2 * c + 1) * S + p] = make_double2(__fma_rn(w, (double)d1.x, x1.x),
+                                                      __fma_rn(w, (double)d1.y, x1.y));
+            }
         }
     }
 }
@@ -2091,9 +2161,9 @@ hipError_t launch_defect(const double2* A, const double2* B, float2* R, const Pl
     return hipGetLastError();
 }
 
-hipError_t launch_accum(double2* X, const float2* D, double w, long long S, long long N,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, S, N);
+hipError_t launch_accum(double2* X, const float2* D, double w, const PlaneCoef* P,
+                        long long nxy, long long S, long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, P, nxy, S, N);
     return hipGetLastError();
 }
 
