@@ -59,10 +59,12 @@ ALG_BYTES_PER_CELL = {
     # complex64 transposed inner sweep: 12 lam + 16 B record + 12 G read,
     # 12 lam written
     "k_adjoint<64,8,AdjPol32>": 304,
-    # complex64 inner sweeps (8 B per value): 12 d + 12 r + 16 B record read,
-    # 12 d written
-    "k_blocked<32,16,2,Pol32>": 304,
-    "k_blocked<32,16,3,Pol32>": 304,
+    # complex64 inner sweeps (8 B per value) in pair-sum form: per H and E
+    # side 3 d + 3 r read and 3 d written where the split pairs are symmetric,
+    # 5 of each on the PML planes, + the 16 B record: 160 B off the PML, 162
+    # at 512^3 with 6-plane PMLs (13 H and 12 E planes not symmetric)
+    "k_blocked<32,16,2,Pol32>": 162,
+    "k_blocked<32,16,3,Pol32>": 162,
 }
 
 
