@@ -154,7 +154,11 @@ int thiim_residual(thiim_ctx *ctx, double *rel_res);
  * 0.3).  The correction added to x is the mean of d over the last
  * Kp = round(2 pi / (omega tau T)) passes of T sweeps -- one period of the
  * modes that an iteration only rotates by e^{-i omega tau}, which the
- * complex64 rounding would otherwise leave in x for ever.
+ * complex64 rounding would otherwise leave in x for ever.  A split pair whose
+ * two parts have identical coefficients on a plane (the z pairs everywhere,
+ * the x and y pairs off the PML) enters a correction through its sum only,
+ * half to each part: a MIXED solve determines the physical fields P x, not
+ * how such a pair is split.
  * *iters (sweeps done, both precisions) and *rel_res may be NULL.
  * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
 int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
