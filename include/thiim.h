@@ -228,12 +228,14 @@ int thiim_autotune(thiim_ctx *ctx, int trial_iters, thiim_tuning *out);
 
 /* A batch advances n contexts together: grids of any size (compact storage,
  * one common stream, each context's own sweep configuration).  Contexts with
- * the same configuration share one launch per pass, whose workgroups cover
- * the concatenated tiles of all of them; the passes of each 64 iterations
- * are captured once in a HIP graph and replayed (eager launches on the null
- * stream, which cannot be captured).  A batch borrows its contexts and a
- * small device workspace (the per-launch item tables); destroy it before
- * them. */
+ * the same configuration share one persistent launch per pass: the resident
+ * workgroups take the concatenated tiles of all of them from a device work
+ * queue (one counter per XCD, reset before each pass).  The passes of each
+ * 64 iterations are captured once in a HIP graph and replayed (eager
+ * launches on the null stream, which cannot be captured).  A batch borrows
+ * its contexts and a small device workspace (the per-launch item tables and
+ * the queue counters); destroy it before them, and do not run two calls on
+ * one batch at the same time. */
 typedef struct thiim_batch thiim_batch;
 
 int thiim_batch_workspace_bytes(int n, size_t *bytes);

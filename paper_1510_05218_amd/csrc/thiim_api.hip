@@ -906,6 +906,8 @@ struct thiim_batch {
     hipStream_t stream;
     char* ws;
     size_t ws_bytes;
+    unsigned int* queue;  // device work queue of the persistent batched passes
+    int ncu;
     std::vector<char> active;
     std::vector<Group> groups;
     bool dirty;
@@ -922,8 +924,13 @@ constexpr int kGraphIters = 64;  // iterations per captured graph (a multiple of
 size_t batch_items_bytes(int n) {
     return align_up((size_t)2 * n * sizeof(thiim::BatchItem), kAlign);
 }
-size_t batch_bytes(int n) {
-    return batch_items_bytes(n) + align_up((size_t)2 * n * sizeof(thiim::BatchItem32), kAlign);
+size_t batch_items32_bytes(int n) {
+    return align_up((size_t)2 * n * sizeof(thiim::BatchItem32), kAlign);
+}
+// item arrays (both kinds), then the 8 counters of the device work queue
+size_t batch_bytes(int n) { return batch_items_bytes(n) + batch_items32_bytes(n) + kAlign; }
+unsigned int* batch_queue(thiim_batch* b, int n) {
+    return (unsigned int*)(b->ws + batch_items_bytes(n) + batch_items32_bytes(n));
 }
 
 void drop_graph(thiim_batch* b) {
@@ -1005,9 +1012,11 @@ hipError_t enqueue(thiim_batch* b, int iters) {
         const int passes = gr.blocked ? iters / 2 : iters;
         for (int p = 0; e == hipSuccess && p < passes; ++p) {
             e = gr.blocked ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                         gr.total, 2, gr.tx, gr.ty, b->stream)
+                                                         gr.total, 2, gr.tx, gr.ty, b->queue,
+                                                         b->ncu, b->stream)
                            : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                       gr.total, gr.tx, gr.ty, b->stream);
+                                                       gr.total, gr.tx, gr.ty, b->queue, b->ncu,
+                                                       b->stream);
             gr.par ^= 1;
             for (int m : gr.members) b->ctx[m]->cur ^= 1;
         }
@@ -1220,7 +1229,8 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                                                    b->ctx[i]->L.S, b->ctx[i]->L.N, b->stream);
                 for (int p = 0; err == hipSuccess && p < P; ++p) {
                     err = thiim::launch_inner32_batch(gr.dev[p & 1], (int)gr.members.size(),
-                                                      gr.total, gr.T, 32, 16, b->stream);
+                                                      gr.total, gr.T, 32, 16, b->queue, b->ncu,
+                                                      b->stream);
                     for (int i : gr.members) {
                         if (err != hipSuccess || p < P - Kp[i]) continue;
                         thiim_ctx* c = b->ctx[i];
@@ -1297,6 +1307,8 @@ int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t wo
     b->stream = ctxs[0]->stream;
     b->ws = (char*)workspace;
     b->ws_bytes = workspace_bytes;
+    b->queue = batch_queue(b, n);
+    b->ncu = ctxs[0]->ncu;
     b->active.assign(n, 1);
     b->dirty = true;
     b->graph = nullptr;
@@ -1415,9 +1427,11 @@ int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
             for (auto& gr : b->groups) {
                 if (e != hipSuccess) break;
                 e = gr.blocked ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                             gr.total, 2, gr.tx, gr.ty, b->stream)
+                                                             gr.total, 2, gr.tx, gr.ty, b->queue,
+                                                             b->ncu, b->stream)
                                : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                           gr.total, gr.tx, gr.ty, b->stream);
+                                                           gr.total, gr.tx, gr.ty, b->queue,
+                                                           b->ncu, b->stream);
             }
             return e;
         };

@@ -122,13 +122,16 @@ hipError_t launch_accum(double2* X, const float2* D, double w, const PlaneCoef* 
 hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
                          hipStream_t s);
 // Batched passes over nitems problems whose tiles total `total` (items in
-// device memory, ordered by tile_begin).
+// device memory, ordered by tile_begin): persistent launches of at most the
+// resident workgroups (ncu CUs) that take tiles from a device work queue of
+// 8 counters at `queue` (reset by the launcher; launches sharing a queue must
+// be ordered on one stream).
 hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
-                              int tile_y, hipStream_t s);
+                              int tile_y, unsigned int* queue, int ncu, hipStream_t s);
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
-                                int ry, hipStream_t s);
+                                int ry, unsigned int* queue, int ncu, hipStream_t s);
 hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
-                                int ry, hipStream_t s);
+                                int ry, unsigned int* queue, int ncu, hipStream_t s);
 // ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all
 // six, 3: E only) into out[0], out[1].
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,

@@ -1246,42 +1246,83 @@ __device__ __forceinline__ Tile batch_tile(const Item& it, int t) {
     return tile_coords<STRIP>(t - it.tile_begin, it.ntx, it.nty);
 }
 
+// Device work queue of the batched passes (persistent launches).  The tile
+// list of a launch is cut into 8 contiguous ranges as xcd_tile deals them,
+// one per XCD; queue[x] counts the tiles handed out of range x.  A workgroup
+// takes the next tile of its own XCD's range (the dispatcher deals
+// workgroups to the XCDs in turn) and, once that range is empty, of the
+// following ranges; it returns when all eight are empty.  Tiles of one pass
+// do not depend on each other, so no workgroup ever waits for another, and
+// every counter grows by at most total + workgroups per launch.
+__global__ void k_queue_reset(unsigned int* __restrict__ queue) {
+    if (threadIdx.x < 8) queue[threadIdx.x] = 0u;
+}
+
+template <class Body>
+__device__ __forceinline__ void run_queue(unsigned int* __restrict__ queue, int total,
+                                          Body&& body) {
+    __shared__ int next_tile;
+    const int home = blockIdx.x & 7;
+    const int q = total / 8, r = total % 8;
+    for (int v = 0; v < 8;) {
+        const int x = (home + v) & 7;
+        if (threadIdx.x == 0) {
+            const unsigned int j = atomicAdd(queue + x, 1u);
+            const int n = q + (x < r ? 1 : 0);
+            next_tile = j < (unsigned int)n ? x * q + min(x, r) + (int)j : -1;
+        }
+        __syncthreads();
+        const int t = next_tile;
+        __syncthreads();
+        if (t < 0) {
+            ++v;
+            continue;
+        }
+        body(t);
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 template <int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_fused_batch(const BatchItem* __restrict__ items,
-                                                        int nitems, int total) {
-    const int t = xcd_tile(total);
-    const int i = batch_find(items, nitems, t);
-    const BatchItem& it = items[i];
-    fused_body<TX, TY>(compact_view(it.cv), it.A, it.B, it.g, it.kchunk, batch_tile<0>(it, t));
+                                                        int nitems, int total,
+                                                        unsigned int* __restrict__ queue) {
+    run_queue(queue, total, [&](int t) {
+        const BatchItem& it = items[batch_find(items, nitems, t)];
+        fused_body<TX, TY>(compact_view(it.cv), it.A, it.B, it.g, it.kchunk,
+                           batch_tile<0>(it, t));
+    });
 }
 
 template <int RX, int RY, int T>
 __global__ __launch_bounds__(RX* RY) void k_inner32_batch(const BatchItem32* __restrict__ items,
-                                                          int nitems, int total) {
-    const int t = xcd_tile(total);
-    const int i = batch_find(items, nitems, t);
-    const BatchItem32& it = items[i];
-    Pol32 pol;
-    pol.ce = it.ce;
-    pol.P32 = it.P32;
-    pol.r = it.r;
-    pol.S = it.S;
-    pol.ph = it.ph;
-    pol.phc = it.phc;
-    pol.ph2 = it.ph2;
-    pol.ph2c = it.ph2c;
-    blocked_body<RX, RY, T>(pol, it.A, it.B, it.g, it.kchunk,
-                            batch_tile<kBlockedStrip>(it, t));
+                                                          int nitems, int total,
+                                                          unsigned int* __restrict__ queue) {
+    run_queue(queue, total, [&](int t) {
+        const BatchItem32& it = items[batch_find(items, nitems, t)];
+        Pol32 pol;
+        pol.ce = it.ce;
+        pol.P32 = it.P32;
+        pol.r = it.r;
+        pol.S = it.S;
+        pol.ph = it.ph;
+        pol.phc = it.phc;
+        pol.ph2 = it.ph2;
+        pol.ph2c = it.ph2c;
+        blocked_body<RX, RY, T>(pol, it.A, it.B, it.g, it.kchunk,
+                                batch_tile<kBlockedStrip>(it, t));
+    });
 }
 
 template <int RX, int RY, int T>
 __global__ __launch_bounds__(RX* RY) void k_blocked_batch(const BatchItem* __restrict__ items,
-                                                          int nitems, int total) {
-    const int t = xcd_tile(total);
-    const int i = batch_find(items, nitems, t);
-    const BatchItem& it = items[i];
-    blocked_body<RX, RY, T>(Pol64<CompactCoefs>{compact_view(it.cv)}, it.A, it.B, it.g,
-                            it.kchunk, batch_tile<kBlockedStrip>(it, t));
+                                                          int nitems, int total,
+                                                          unsigned int* __restrict__ queue) {
+    run_queue(queue, total, [&](int t) {
+        const BatchItem& it = items[batch_find(items, nitems, t)];
+        blocked_body<RX, RY, T>(Pol64<CompactCoefs>{compact_view(it.cv)}, it.A, it.B, it.g,
+                                it.kchunk, batch_tile<kBlockedStrip>(it, t));
+    });
 }
 
 
@@ -1971,55 +2012,73 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                       : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
 }
 
-hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
-                              int tile_y, hipStream_t s) {
-    if (nitems < 1 || total < 1) return hipErrorInvalidValue;
-    if (tile_x == 64 && tile_y == 8)
-        hipLaunchKernelGGL((k_fused_batch<64, 8>), dim3(total), dim3(512), 0, s, items, nitems,
-                           total);
-    else if (tile_x == 32 && tile_y == 8)
-        hipLaunchKernelGGL((k_fused_batch<32, 8>), dim3(total), dim3(256), 0, s, items, nitems,
-                           total);
-    else if (tile_x == 64 && tile_y == 4)
-        hipLaunchKernelGGL((k_fused_batch<64, 4>), dim3(total), dim3(256), 0, s, items, nitems,
-                           total);
-    else if (tile_x == 16 && tile_y == 16)
-        hipLaunchKernelGGL((k_fused_batch<16, 16>), dim3(total), dim3(256), 0, s, items, nitems,
-                           total);
-    else
-        return hipErrorInvalidValue;
+// Persistent launch of a batched pass: the queue reset, then as many
+// workgroups as the device holds at once (the kernel's occupancy times the
+// CUs), at most one per tile.
+template <auto K>
+static int blocks_per_cu(int block) {
+    static const int nb = [block] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, reinterpret_cast<const void*>(K),
+                                                         block, 0) != hipSuccess ||
+            v < 1)
+            v = 1;
+        return v;
+    }();
+    return nb;
+}
+
+template <auto K, class Item>
+static hipError_t launch_queued(int block, const Item* items, int nitems, int total,
+                                unsigned int* queue, int ncu, hipStream_t s) {
+    const long long resident = (long long)blocks_per_cu<K>(block) * (ncu > 0 ? ncu : 256);
+    const int grid = (int)(total < resident ? total : resident);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&items, (void*)&nitems, (void*)&total, (void*)&queue};
+    e = hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
+                              int tile_y, unsigned int* queue, int ncu, hipStream_t s) {
+    if (nitems < 1 || total < 1 || !queue) return hipErrorInvalidValue;
+    if (tile_x == 64 && tile_y == 8)
+        return launch_queued<k_fused_batch<64, 8>>(512, items, nitems, total, queue, ncu, s);
+    if (tile_x == 32 && tile_y == 8)
+        return launch_queued<k_fused_batch<32, 8>>(256, items, nitems, total, queue, ncu, s);
+    if (tile_x == 64 && tile_y == 4)
+        return launch_queued<k_fused_batch<64, 4>>(256, items, nitems, total, queue, ncu, s);
+    if (tile_x == 16 && tile_y == 16)
+        return launch_queued<k_fused_batch<16, 16>>(256, items, nitems, total, queue, ncu, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
-                                int ry, hipStream_t s) {
-    if (nitems < 1 || total < 1 || T != 2) return hipErrorInvalidValue;
+                                int ry, unsigned int* queue, int ncu, hipStream_t s) {
+    if (nitems < 1 || total < 1 || T != 2 || !queue) return hipErrorInvalidValue;
     if (rx == 64 && ry == 8)
-        hipLaunchKernelGGL((k_blocked_batch<64, 8, 2>), dim3(total), dim3(512), 0, s, items,
-                           nitems, total);
-    else if (rx == 64 && ry == 6)
-        hipLaunchKernelGGL((k_blocked_batch<64, 6, 2>), dim3(total), dim3(384), 0, s, items,
-                           nitems, total);
-    else if (rx == 32 && ry == 16)
-        hipLaunchKernelGGL((k_blocked_batch<32, 16, 2>), dim3(total), dim3(512), 0, s, items,
-                           nitems, total);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch_queued<k_blocked_batch<64, 8, 2>>(512, items, nitems, total, queue, ncu, s);
+    if (rx == 64 && ry == 6)
+        return launch_queued<k_blocked_batch<64, 6, 2>>(384, items, nitems, total, queue, ncu, s);
+    if (rx == 32 && ry == 16)
+        return launch_queued<k_blocked_batch<32, 16, 2>>(512, items, nitems, total, queue, ncu,
+                                                         s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
-                                int ry, hipStream_t s) {
-    if (nitems < 1 || total < 1 || rx != 32 || ry != 16) return hipErrorInvalidValue;
+                                int ry, unsigned int* queue, int ncu, hipStream_t s) {
+    if (nitems < 1 || total < 1 || rx != 32 || ry != 16 || !queue) return hipErrorInvalidValue;
     if (T == 2)
-        hipLaunchKernelGGL((k_inner32_batch<32, 16, 2>), dim3(total), dim3(512), 0, s, items,
-                           nitems, total);
-    else if (T == 3)
-        hipLaunchKernelGGL((k_inner32_batch<32, 16, 3>), dim3(total), dim3(512), 0, s, items,
-                           nitems, total);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch_queued<k_inner32_batch<32, 16, 2>>(512, items, nitems, total, queue, ncu,
+                                                         s);
+    if (T == 3)
+        return launch_queued<k_inner32_batch<32, 16, 3>>(512, items, nitems, total, queue, ncu,
+                                                         s);
+    return hipErrorInvalidValue;
 }
 
 template <class AP>
