@@ -491,7 +491,10 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(pb)
     out = {
-        "metric": "THIIM GLUP/s (512^3, complex128, 100 iterations)",
+        # the headline metric as a whole: value is its first part (GLUP/s of the
+        # 512^3 workload, config), the roofline entry the second, solve_1e-8
+        # the third (solves/s at relative residual 1e-8, mixed vs plain FP64)
+        "metric": "THIIM GLUP/s & % HBM roofline; solves/s at rel. residual 1e-8 vs plain FP64",
         "value": glups,
         "unit": "GLUP/s",
         "n_gpus": 1,
