@@ -286,8 +286,11 @@ class Solver:
                               problem.bcy, kernel, t_block, tile, z_chunk,
                               self.stream.cuda_stream, storage, precision, adjoint)
         self.ws_bytes = thiim_workspace_bytes(self.grid)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        # allocated on the stream the library runs on, so that torch's caching
+        # allocator never hands the memory to another stream while kernels of
+        # this context may still use it
         with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
             eps = self._to_dev(problem.eps)
             srcs = [self._to_dev(problem.sources[k]) if k in problem.sources else None
                     for k in ("Hx", "Hy", "Ex", "Ey")]
@@ -369,6 +372,7 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
+            self.stream.synchronize()  # no kernel of this context still runs
             thiim_destroy(self.ctx)
             self.ctx = None
             self.workspace = None
@@ -396,7 +400,8 @@ class Batch:
                                **solver_kw) for p in problems]
         self.n = len(self.solvers)
         self.ws_bytes = thiim_batch_workspace_bytes(self.n)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.batch = thiim_batch_create([s.ctx for s in self.solvers],
                                         self.workspace.data_ptr(), self.ws_bytes)
         self.tuning = (thiim_batch_autotune(self.batch, trial_iters).as_dict() if autotune
@@ -416,6 +421,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "batch", None) is not None:
+            self.stream.synchronize()
             thiim_batch_destroy(self.batch)
             self.batch = None
         for s in getattr(self, "solvers", []):
