@@ -311,3 +311,23 @@ def test_full_size_textured_512_every_cell(capsys):
         print(f"[512 every cell] part {q}: norm {ref:.3e}, error {err:.2e}", flush=True)
         assert ref > 0 and err <= 1e-12 * total
     assert np.linalg.norm(x - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+def test_invalid_material_rejected_at_create():
+    """eps' = 0 (neither Eq. 3 nor Eq. 5 applies) and non-finite eps are
+    found by the coefficient kernel and reported as THIIM_EINVAL by
+    thiim_create; a valid problem on the same device still works after."""
+    _require_gpu()
+    for bad in (0.0 + 0.3j, complex(float("nan"), 0.0), complex(2.0, float("inf"))):
+        for storage in ("full", "compact"):
+            pb = inputs.random_problem(9, 7, 6, seed=4)
+            pb.eps[3, 2, 5] = bad
+            with pytest.raises(thiim.ThiimError) as e:
+                thiim.Solver(pb, storage=storage)
+            assert e.value.status == thiim.THIIM_EINVAL, (bad, storage)
+            assert "eps" in thiim.last_error()
+    pb = inputs.random_problem(9, 7, 6, seed=4)
+    s, x = _gpu_run(pb, 5, kernel="blocked", storage="compact")
+    s.close()
+    _, xo = _oracle_run(pb, 5)
+    assert _rel(x.cpu().numpy(), xo) < 1e-12
