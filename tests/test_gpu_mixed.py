@@ -119,3 +119,40 @@ def test_mixed_dirichlet_back_iteration_reaches_direct_solve(bcx, bcy):
     # slow convergence (the error shrinks by ~0.06% per iteration) magnifies
     # the residual into the error
     assert _rel(_phys(s.fields()), oracle.physical(xs)) < 1e-6
+
+
+def test_first_correction_full_size_512():
+    """The first-correction identity on the 512^3 benchmark workload in the
+    configuration the mixed solves use (T = 3, automatic chunks): the
+    physical fields of one correction from x0 = 0 equal the window mean of
+    plain FP64 iterates.  Tolerance 1e-5: about 60 complex64 sweeps, each
+    rounding at 6e-8 relative."""
+    _require_gpu()
+    if torch.cuda.get_device_properties(0).total_memory < 250e9:
+        pytest.skip("needs the 288 GB of an MI355X")
+    n, T, m = 512, 3, 9
+    pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200)
+    kp = _window_passes(pb, T)
+    passes = max((m - 1 + T - 1) // T, kp)
+    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=T)
+    rc, it, r = s.solve(1e-30, 2, m)
+    assert rc == thiim.THIIM_ENOTCONV and it == 2 + passes * T
+    x = s.fields()
+    x_mixed = x[0::2] + x[1::2]
+    del x
+    s.close()
+    torch.cuda.empty_cache()
+    f = thiim.Solver(pb, storage="compact", kernel="blocked")
+    f.iterate(1 + (passes - kp + 1) * T)
+    x = f.fields()
+    acc = (x[0::2] + x[1::2]) / kp
+    for _ in range(kp - 1):
+        f.iterate(T)
+        x = f.fields()
+        acc += (x[0::2] + x[1::2]) / kp
+    del x
+    f.close()
+    err = float(torch.linalg.vector_norm(x_mixed - acc) / torch.linalg.vector_norm(acc))
+    print(f"[512 first correction] {passes} passes of T = {T}, rel. error {err:.2e}",
+          flush=True)
+    assert err < 1e-5
