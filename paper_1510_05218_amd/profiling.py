@@ -20,7 +20,7 @@
 
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
-    python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD
+    python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD [NAME,NAME...]
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
     python -m paper_1510_05218_amd.profiling run_c3 [n]
@@ -54,6 +54,9 @@ ALG_BYTES_PER_CELL = {
     "k_blocked<64,8,2,Pol64<CompactCoefs>>": 400,
     # transposed sweep: 12 lam + eps + 3 g read, 12 written
     "k_adjoint<64,8,AdjPol64<false>>": 448,
+    # batched passes: the same per-cell bytes, over all problems of a launch
+    "k_blocked_batch<32,16,2>": 400,
+    "k_fused_batch<64,8>": 400,
     # with a source on every part (defect correction): 12 lam + eps + 12 G
     "k_adjoint<64,8,AdjPol64<true>>": 592,
     # complex64 transposed inner sweep: 12 lam + 16 B record + 12 G read,
@@ -134,8 +137,13 @@ def traffic_summary(fetch_csv, write_csv, n_cells, out_json, command, scales=Non
     return out
 
 
-def kernel_stats_md(stats_csv, n_cells, out_md, command):
+def kernel_stats_md(stats_csv, n_cells, out_md, command, only=None):
+    """only: comma-separated substrings; keep the kernels whose name holds one
+    (n_cells must then be the cells one launch of each kept kernel covers)."""
     rows = list(csv.DictReader(open(stats_csv)))
+    if only:
+        keys = only.split(",")
+        rows = [r for r in rows if any(k in r["Name"] for k in keys)]
     lines = ["# THIIM kernels: rocprofv3 kernel statistics", "",
              "Command:", "", "```", command, "```", "",
              f"Grid: {n_cells} cells.  Achieved = algorithmic bytes per launch / average "
@@ -327,7 +335,7 @@ def main(argv):
         print(json.dumps(traffic_summary(fetch, write, int(n), out, cmd, scales), indent=1))
     elif argv[0] == "stats":
         stats, n, out, cmd = argv[1:5]
-        kernel_stats_md(stats, int(n), out, cmd)
+        kernel_stats_md(stats, int(n), out, cmd, argv[5] if len(argv) > 5 else None)
         print(open(out).read())
     elif argv[0] == "run_mixed":
         run_mixed(int(argv[1]) if len(argv) > 1 else 512)
