@@ -128,8 +128,10 @@ typedef struct {
  * per-plane tables and reduction scratch; 256-byte aligned. */
 int thiim_workspace_bytes(const thiim_grid *g, size_t *bytes);
 
-/* Validates the inputs, builds the 28 coefficient arrays on the device
- * (Eq. (3)-(5) solved for the new value), zeroes the fields (x0 = 0) and
+/* Validates the inputs, builds the coefficient data on the device (Eq.
+ * (3)-(5) solved for the new value: the 28 arrays with full storage; eps,
+ * the 4 Src arrays and per-plane tables with compact storage; the complex64
+ * records with mixed precision), zeroes the fields (x0 = 0) and
  * records ||P Phi(0)||_2 for thiim_residual (P: sum of each split pair).
  * omega: angular frequency in units of c0/h.  Synchronising.  On failure
  * *out is NULL. */
