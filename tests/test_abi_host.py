@@ -91,3 +91,21 @@ def test_solver_refuses_cpu():
     pb = inputs.solar_cell(8, 8, 16, seed=1, npml=3)
     with pytest.raises(RuntimeError):
         thiim.Solver(pb, device="cpu")
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises at first use: there
+    is no CPU fallback."""
+    import subprocess
+    import sys
+
+    code = ("import paper_1510_05218_amd.thiim as t\n"
+            "try:\n"
+            "    t.lib()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    env = dict(os.environ, THIIM_LIBRARY="/nonexistent/libthiim.so")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "no CPU fallback" in r.stdout
