@@ -366,3 +366,33 @@ def test_memory_light_mode_bitwise(oracle_lib, bcx, bcy):
     b = oracle.iterate_light(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h,
                              oracle.zero_fields(pb.shape), 9, bcx, bcy)
     assert np.array_equal(a, b)
+
+
+def test_spectral_radius_of_the_iteration(oracle_lib):
+    """Convergence of the iteration matrix M = Phi(.) - Phi(0) by power
+    iteration from a random split state on a lossy stack with PML: the
+    dominant eigenvalue is exactly e^{-i w tau} (the curl-free H and the split
+    differences that one iteration only rotates, R16/R17), so rho(M) = 1 on
+    the split space rather than < 1, and that eigenvalue is defective: the
+    norm ratio approaches 1 like 1 + O(1/n) (polynomial, not exponential,
+    growth of the split differences it drives).  The physical residual and
+    divergence-free sources keep the solver off this subspace; convergence of
+    the physical fields is pinned by test_iteration_converges_to_fixed_point."""
+    pb = inputs.random_problem(6, 5, 12, seed=31, npml=3, loss_range=(0.3, 0.8))
+    coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, {}, pb.omega, pb.tau, pb.h)
+    g = inputs.rng(32)
+    x = g.standard_normal((12,) + pb.shape) + 1j * g.standard_normal((12,) + pb.shape)
+    x /= np.linalg.norm(x)
+    lam_ref = np.exp(-1j * pb.omega * pb.tau)
+    ratio = {}
+    for n in range(1, 3001):
+        y = oracle.phi(coef, x)
+        r = np.linalg.norm(y)
+        if n in (1000, 3000):
+            ratio[n] = r
+            lam = np.vdot(x, y) / np.vdot(x, x)
+        x = y / r
+    assert abs(lam - lam_ref) < 1e-3
+    assert 1.0 <= ratio[3000] < 1.0 + 1e-3
+    # an eigenvalue of modulus > 1 would hold the ratio above 1 at a constant
+    assert ratio[3000] - 1.0 < 0.6 * (ratio[1000] - 1.0)
