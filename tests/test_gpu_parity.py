@@ -73,6 +73,22 @@ def test_c1_layered_textured_200_iterations(kernel, storage):
     assert _rel(xg.cpu().numpy(), xo) < 1e-12
 
 
+def test_128cubed_random_media_20_iterations():
+    """128^3 cells of per-cell random media with back-iteration cells and
+    random sources on all four source arrays (every cell and part active from
+    the first iteration), 20 iterations: every sweep form against the oracle
+    (1e-12) and bit-identical to each other."""
+    _require_gpu()
+    pb = _with_back_cells(inputs.random_problem(128, 128, 128, seed=29, npml=6), 30)
+    _, xo = _oracle_run(pb, 20)
+    _, xn = _gpu_run(pb, 20, kernel="naive", storage="full")
+    assert _rel(xn.cpu().numpy(), xo) < 1e-12
+    for kernel, storage in (("fused", "compact"), ("blocked", "compact"), ("blocked", "full")):
+        s, x = _gpu_run(pb, 20, kernel=kernel, storage=storage)
+        s.close()
+        assert torch.equal(x, xn), (kernel, storage)
+
+
 @pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_random_ragged_problem(bcx, bcy):
     """Per-cell random materials with back-iteration cells, random sources on
