@@ -71,6 +71,19 @@ ALG_BYTES_PER_CELL = {
 }
 
 
+def code_balance(rx, ry, t, b_read, b_write, nx, ny):
+    """Modelled HBM bytes per lattice-site update of a temporally blocked
+    sweep with overlapped tiles (the GPU form of the paper's Eq. 12): regions
+    of rx x ry columns store their centre (rx - 2t) x (ry - 2t) after t
+    iterations per pass; each pass reads b_read bytes for every region cell
+    (ring included, tiles rounded up to cover nx x ny) and writes b_write
+    bytes per stored cell."""
+    ox, oy = rx - 2 * t, ry - 2 * t
+    tiles_x, tiles_y = -(-nx // ox), -(-ny // oy)
+    read_per_cell = b_read * tiles_x * tiles_y * rx * ry / (nx * ny)
+    return (read_per_cell + b_write) / t
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")

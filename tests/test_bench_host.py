@@ -69,3 +69,22 @@ def test_traffic_summary_scales_by_calibration_copy(tmp_path):
     assert k["bytes_per_cell"] == (512000.0 + 307200.0) / n
     assert k["alg_bytes_per_cell"] == 400
     assert json.load(open(tmp_path / "t.json"))["source_hash"] == profiling.source_hash()
+
+
+def test_code_balance_model_against_committed_counters():
+    """The overlapped-tile code-balance model against the committed rocprofv3
+    counter summaries of the 512^3 sweeps: the measured bytes lie at or below
+    the model (ring re-reads that hit in L2 are not HBM traffic) and above
+    70% of it."""
+    n = 512
+    m64 = profiling.code_balance(32, 16, 2, 13 * 16, 12 * 16, n, n)
+    assert abs(m64 - 261.953125) < 1e-9
+    cases = [("traffic_thiim_512cubed.json", "k_blocked<32,16,2,Pol64<CompactCoefs>>", 2, m64),
+             ("traffic_mixed_inner_512cubed.json", "k_blocked<32,16,3,Pol32>", 3,
+              profiling.code_balance(32, 16, 3, 112, 48, n, n)),
+             ("traffic_mixed_inner_512cubed.json", "k_blocked<32,16,2,Pol32>", 2,
+              profiling.code_balance(32, 16, 2, 112, 48, n, n))]
+    for fname, kernel, t, model in cases:
+        k = json.load(open(os.path.join(ROOT, "profiles", fname)))["kernels"][kernel]
+        measured = k["bytes_per_cell"] / t
+        assert 0.7 * model <= measured <= 1.0 * model, (kernel, measured, model)
