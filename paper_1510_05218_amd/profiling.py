@@ -15,6 +15,7 @@
   problem, mixed solver against the plain FP64 iteration.
 * ``run_c3``: the mixed solver on the n^3 benchmark problem to 1e-8 and on
   to 1e-10; the error of the 1e-8 solution against the 1e-10 one.
+* ``run_c5``: time to the adjoint gradient on the 128 x 128 x 256 stack.
 * ``run_spectral``: the full batched spectral sweep (32 wavelengths x 4
   geometries up to 192 x 192 x 384) to 1e-8 in resident waves.
 
@@ -24,6 +25,7 @@ Usage:
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
     python -m paper_1510_05218_amd.profiling run_c3 [n]
+    python -m paper_1510_05218_amd.profiling run_c5
     python -m paper_1510_05218_amd.profiling run_spectral [waves]
 """
 from __future__ import annotations
@@ -291,6 +293,34 @@ def run_c3(n=512, tol=1e-8, ref_tol=1e-10, m=2000):
     print(json.dumps(out), flush=True)
 
 
+def run_c5(tol=1e-10, m=2000):
+    """Time to the gradient on the adjoint configuration: a 128 x 128 x 256
+    textured stack (seed 20, eps'' in [0.1, 0.5]), J over the middle layer;
+    the forward state by the mixed solver and the adjoint by averaged defect
+    correction with complex64 inner sweeps, both to tol."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import inputs, thiim
+
+    pb = inputs.solar_cell(128, 128, 256, seed=20, npml=6, loss_range=(0.1, 0.5))
+    w = (pb.eps == pb.layers[1][2]).astype(np.float64)
+    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=3, adjoint=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    rc, n_fw, r = s.solve(tol, 2000000, m)
+    t1 = time.time()
+    rc2, J, grad, n_adj, ar = s.adjoint_grad(w, tol=tol, max_it=2000000, check_every=m)
+    t2 = time.time()
+    s.close()
+    print(json.dumps({"grid": "128x128x256", "tol": tol, "forward_status": rc,
+                      "forward_sweeps": n_fw, "forward_s": t1 - t0, "adjoint_status": rc2,
+                      "adjoint_sweeps": n_adj, "adjoint_s": t2 - t1, "J": J,
+                      "gradient_total_s": t2 - t0}), flush=True)
+
+
 SPECTRAL_GEOMETRIES = [(64, 64, 64, 10), (96, 96, 128, 11), (128, 128, 256, 12),
                        (192, 192, 384, 13)]
 
@@ -356,6 +386,8 @@ def main(argv):
         run_solve_512(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_c3":
         run_c3(int(argv[1]) if len(argv) > 1 else 512)
+    elif argv[0] == "run_c5":
+        run_c5()
     elif argv[0] == "run_spectral":
         run_spectral(argv[1] if len(argv) > 1 else "0,1,2:3a:3b:3c")
     else:
