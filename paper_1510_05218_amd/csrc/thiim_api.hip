@@ -659,19 +659,26 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
             e = thiim::launch_sub(c->lam[0], c->lam[1], S, N, c->stream);  // r
             if (c->ce32) {
                 // mixed-precision context: complex64 inner sweeps (its r32 and
-                // d32 buffers), the defect and lam in FP64
+                // d32 buffers), two per pass of the temporally blocked
+                // transposed sweep, averaged over the passes of one rotation
+                // period; the defect and lam in FP64
                 if (e == hipSuccess) e = thiim::launch_to32(c->lam[1], c->r32, S, N, c->stream);
                 if (e == hipSuccess) e = thiim::launch_copy32(c->r32, c->d32[0], S, N, c->stream);
+                constexpr int T2 = 2;
+                int Kq = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau * T2));
+                if (Kq < 1) Kq = 1;
+                const int passes = (m + T2 - 1) / T2 > Kq ? (m + T2 - 1) / T2 : Kq;
                 int di = 0;
-                for (int p = 0; e == hipSuccess && p < m; ++p) {
-                    e = thiim::launch_adjoint32(c->cv, c->ce32, c->p32, c->d32[di],
-                                                c->d32[1 - di], c->r32, c->geo, c->tile_x,
-                                                c->tile_y, c->z_chunk, c->stream);
+                for (int p = 0; e == hipSuccess && p < passes; ++p) {
+                    e = thiim::launch_adjoint32_blocked(c->cv, c->ce32, c->p32, c->d32[di],
+                                                        c->d32[1 - di], c->r32, c->geo, T2, 32,
+                                                        16, c->bz_chunk, c->stream);
                     di = 1 - di;
-                    if (e == hipSuccess && p >= m - Kp)
-                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kp, nullptr, 0, S,
+                    if (e == hipSuccess && p >= passes - Kq)
+                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kq, nullptr, 0, S,
                                                 N, c->stream);
                 }
+                done += passes * T2 - m;  // counted below as m
             } else {
                 if (e == hipSuccess)
                     e = thiim::launch_copy(c->lam[1], c->lam[2], 12 * S, c->stream);

@@ -147,6 +147,11 @@ hipError_t launch_adjoint(const CoefView& cv, const double2* A, double2* B, cons
 hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
                             const float2* A, float2* B, const float2* R, const Geo& g,
                             int tile_x, int tile_y, int kchunk, hipStream_t s);
+// T = 2 transposed iterations per pass (regions of 32 x 16 columns) of the
+// same complex64 sweep; chunk planes per workgroup stream
+hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                                    const float2* A, float2* B, const float2* R, const Geo& g,
+                                    int T, int rx, int ry, int kchunk, hipStream_t s);
 // 12-array FP64 helpers: Y -= X; X += w D.
 hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s);
 hipError_t launch_to32(const double2* X, float2* R, long long S, long long N, hipStream_t s);

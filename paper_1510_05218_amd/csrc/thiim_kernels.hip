@@ -1657,6 +1657,206 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V*
     }
 }
 
+// ---------------------------------------------------------------------------
+// Temporally blocked transposed sweep of the complex64 inner passes of the
+// adjoint defect correction: T iterations lam <- M^T lam + G per HBM pass,
+// the structure of blocked_body with the phases of k_adjoint.  A workgroup
+// covers RX x RY columns (one thread each, lanes along x) and streams z; at
+// step k stage s runs phases 1-2 (u = c_E lam_E, then the H transpose) at
+// plane kh = k - s + 1 and phase 3 (the E transpose) at plane ke = k - s,
+// so one read of plane k feeds all stages.  Phase 2 takes u at -x / -y and
+// phase 3 v = c_H lam_H' at +x / +y through LDS -- the neighbour pattern of
+// the forward H and E half-steps -- so after T stages the centre
+// (RX - 2T) x (RY - 2T) is exact and stored, z chunks overlap by T - 1
+// planes, and the ring is recomputed by the neighbouring workgroups.  Every
+// cell's arithmetic is k_adjoint's, operation for operation; what a stage
+// hands to the next plane or the next stage stays in registers: t_E lam_E,
+// the z parts of u and v, lam_H, the coefficient record and the source.
+// ---------------------------------------------------------------------------
+template <int RX, int RY, int T>
+__global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
+                                                              const float2* __restrict__ A,
+                                                              float2* __restrict__ B,
+                                                              const float2* __restrict__ G,
+                                                              Geo g, int kchunk) {
+    using V = float2;
+    constexpr int R = RX * RY;
+    constexpr int OX = RX - 2 * T, OY = RY - 2 * T;
+    static_assert(OX >= 1 && OY >= 1, "region too small for T stages");
+    __shared__ V U[T][4][R];     // u1, u3, u4, u5 of stage s at its plane kh
+    __shared__ V W[T][2][4][R];  // v1, v3, v4, v5 of stage s, by plane parity
+
+    const Tile TT = tile_of<kBlockedStrip>((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
+                                           (g.nz + kchunk - 1) / kchunk);
+    const long long S = g.S;
+    const long long plane = (long long)g.nx * g.ny;
+    const int lane = threadIdx.x % RX, row = threadIdx.x / RX;
+    const int ux = TT.bx * OX - T + lane;
+    const int uy = TT.by * OY - T + row;
+    int gi = ux, gj = uy;
+    const bool valid = resolve_xy(g, gi, gj);
+    const bool own = lane >= T && lane < RX - T && row >= T && row < RY - T &&
+                     ux < g.nx && uy < g.ny;
+    const uint32_t bo = valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
+    const int me = row * RX + lane;
+    const int xm = row * RX + (lane > 0 ? lane - 1 : 0);
+    const int xp = row * RX + (lane < RX - 1 ? lane + 1 : RX - 1);
+    const int ym = (row > 0 ? row - 1 : 0) * RX + lane;
+    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * RX + lane;
+    const int k0 = TT.bz * kchunk;
+    const int k1 = min(g.nz, k0 + kchunk);
+    const int ks = max(0, k0 - (T - 1));
+    const int kend = min(k1 + T - 1, g.nz + T - 1);
+    const V* AE = A + 6 * S;
+    V* BE = B + 6 * S;
+    const V* GE = G + 6 * S;
+    const V Z = vzero<V>();
+
+    for (int i = threadIdx.x; i < T * 4 * R; i += R) {
+        (&U[0][0][0])[i] = Z;
+        (&W[0][0][0][0])[i] = Z;
+        (&W[0][0][0][0])[i + T * 4 * R] = Z;
+    }
+    // carried state of stage s at index s - 1
+    V ep[T][6];   // t_E lam_E at plane kh - 1 (phase 1 of the previous step)
+    V hc[T][6];   // lam_H of stage s - 1 at plane kh (stages >= 2)
+    V gh[T][6];   // G of the H parts at plane kh (stages >= 2)
+    V ge[T][6];   // G of the E parts at plane ke (stages >= 2)
+    V u0m[T], u2m[T];  // z parts of u at plane kh - 1
+    V vz0[T], vz2[T];  // z parts of v at plane ke (own v1, v3, v4, v5: in W)
+    float4 rec[T];     // E-coefficient record at plane kh (stages >= 2)
+#pragma unroll
+    for (int s = 0; s < T; ++s) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ep[s][q] = hc[s][q] = gh[s][q] = ge[s][q] = Z;
+        u0m[s] = u2m[s] = vz0[s] = vz2[s] = Z;
+        rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    if (ks > 0 && valid) {  // u of plane ks - 1 for stage 1
+        const long long po = (ks - 1) * plane;
+        V t[6], c[6];
+        ap.p.ecoef_c(ks - 1, ap.p.load_crec(po, bo), t, c);
+        u0m[0] = cmul(c[0], ldo(AE + 0 * S + po, bo));
+        u2m[0] = cmul(c[2], ldo(AE + 2 * S + po, bo));
+    }
+    __syncthreads();
+
+    for (int k = ks; k <= kend; ++k) {
+        const int par = k & 1;
+        // the reads of the step, all issued before its first barrier
+        V lE[6], lH[6], gH0[6], gE0[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) lE[q] = lH[q] = gH0[q] = gE0[q] = Z;
+        float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (k < g.nz && valid) {
+            load6v(AE, S, k * plane, bo, lE);
+            load6v(A, S, k * plane, bo, lH);
+            load6v(G, S, k * plane, bo, gH0);
+            r0 = ap.p.load_crec(k * plane, bo);
+        }
+        if (valid && k >= 1 && k - 1 < g.nz) load6v(GE, S, (k - 1) * plane, bo, gE0);
+
+        V eo[6];  // lam_E handed from stage s to stage s + 1 (plane ke)
+        V hn[T][6], en_n[T][6], u0n[T], u2n[T], v0n[T], v2n[T];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) eo[q] = Z;
+#pragma unroll
+        for (int s = 1; s <= T; ++s) {
+            const int kh = k - s + 1, ke = k - s;
+            const bool hin = valid && kh >= 0 && kh < g.nz;
+            // ---- phase 1: u = c_E lam_E and t_E lam_E at plane kh
+            V u[6], en[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) u[q] = en[q] = Z;
+            if (hin) {
+                V t[6], c[6];
+                ap.p.ecoef_c(kh, s == 1 ? r0 : rec[s - 1], t, c);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const V l = s == 1 ? lE[q] : eo[q];
+                    u[q] = cmul(c[q], l);
+                    en[q] = cmul(t[q], l);
+                }
+            }
+            U[s - 1][0][me] = u[1];
+            U[s - 1][1][me] = u[3];
+            U[s - 1][2][me] = u[4];
+            U[s - 1][3][me] = u[5];
+            __syncthreads();
+            // ---- phase 2: lam_H' = lam_H + D_E^T u at plane kh
+            V v[6], ho[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] = ho[q] = Z;
+            if (hin) {
+                const V inc[3] = {
+                    csub(csub(u2m[s - 1], u[2]), csub(U[s - 1][2][ym], u[4])),
+                    csub(csub(U[s - 1][3][xm], u[5]), csub(u0m[s - 1], u[0])),
+                    csub(csub(U[s - 1][0][ym], u[1]), csub(U[s - 1][1][xm], u[3]))};
+                V t[6], c[6];
+                ap.hcoef(kh, t, c);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const V lh = cadd(s == 1 ? lH[q] : hc[s - 1][q], inc[q / 2]);
+                    v[q] = cmul(c[q], lh);
+                    ho[q] = cadd(cmul(t[q], lh), s == 1 ? gH0[q] : gh[s - 1][q]);
+                }
+                if (s == T && own && kh >= k0 && kh < k1) store6v(B, S, kh * plane, bo, ho);
+            }
+            // ---- phase 3: lam_E = t_E lam_E + D_H^T v at plane ke
+            V eout[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) eout[q] = Z;
+            if (valid && ke >= 0 && ke < g.nz) {
+                const int pq = par ^ 1;  // v of plane ke, written at the previous step
+                const V inc[3] = {
+                    csub(csub(W[s - 1][pq][2][me], W[s - 1][pq][2][yp]), csub(vz2[s - 1], v[2])),
+                    csub(csub(vz0[s - 1], v[0]), csub(W[s - 1][pq][3][me], W[s - 1][pq][3][xp])),
+                    csub(csub(W[s - 1][pq][1][me], W[s - 1][pq][1][xp]),
+                         csub(W[s - 1][pq][0][me], W[s - 1][pq][0][yp]))};
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    eout[q] = cadd(cadd(ep[s - 1][q], inc[q / 2]), s == 1 ? gE0[q] : ge[s - 1][q]);
+                if (s == T && own && ke >= k0 && ke < k1) store6v(BE, S, ke * plane, bo, eout);
+            }
+            // v of plane kh for phase 3 of the next step (the other parity)
+            W[s - 1][par][0][me] = v[1];
+            W[s - 1][par][1][me] = v[3];
+            W[s - 1][par][2][me] = v[4];
+            W[s - 1][par][3][me] = v[5];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                hn[s - 1][q] = ho[q];
+                en_n[s - 1][q] = en[q];
+                eo[q] = eout[q];
+            }
+            u0n[s - 1] = u[0];
+            u2n[s - 1] = u[2];
+            v0n[s - 1] = v[0];
+            v2n[s - 1] = v[2];
+        }
+        // ---- shift the carried state one plane
+#pragma unroll
+        for (int s = T - 1; s >= 1; --s) {
+            rec[s] = s == 1 ? r0 : rec[s - 1];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                hc[s][q] = hn[s - 1][q];
+                gh[s][q] = s == 1 ? gH0[q] : gh[s - 1][q];
+                ge[s][q] = s == 1 ? gE0[q] : ge[s - 1][q];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < T; ++s) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) ep[s][q] = en_n[s][q];
+            u0m[s] = u0n[s];
+            u2m[s] = u2n[s];
+            vz0[s] = v0n[s];
+            vz2[s] = v2n[s];
+        }
+    }
+}
+
 // Objective J = sum w eps'' |E|^2 of the state X and the adjoint source
 // g = dJ/dx: g_a = w eps'' conj(E_a) for each physical E component a (both
 // of its parts receive it).  G: 3 arrays.  Block partial sums of J (and of
@@ -2127,6 +2327,26 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
     ap.p.ph2 = to32(cv.K.ph2);
     ap.p.ph2c = to32(cv.K.ph2c);
     return adjoint_impl(ap, A, B, R, g, tile_x, tile_y, kchunk, s);
+}
+
+hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
+                                    const float2* A, float2* B, const float2* R, const Geo& g,
+                                    int T, int rx, int ry, int kchunk, hipStream_t s) {
+    if (!cv.compact || T != 2 || rx != 32 || ry != 16) return hipErrorInvalidValue;
+    AdjPol32 ap;
+    ap.p.ce = ce;
+    ap.p.P32 = P32;
+    ap.p.r = nullptr;
+    ap.p.S = cv.S;
+    ap.p.ph = to32(cv.K.ph);
+    ap.p.phc = to32(cv.K.phc);
+    ap.p.ph2 = to32(cv.K.ph2);
+    ap.p.ph2c = to32(cv.K.ph2c);
+    const int ox = rx - 2 * T, oy = ry - 2 * T;
+    dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
+    hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2>), grid, dim3(512), 0, s, ap, A, B, R, g,
+                       kchunk);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_source(const double2* X, const double2* eps, const double* w, long long S,
