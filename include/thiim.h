@@ -190,7 +190,11 @@ int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
  *             conductivity is small), until tol or max_it sweeps
  *             (THIIM_ENOTCONV; the outputs are still written).  On a
  *             THIIM_PRECISION_MIXED context the inner sweeps run in
- *             complex64; the defect, lam and the norms stay in FP64.
+ *             complex64, two per pass of a temporally blocked transposed
+ *             sweep (32 x 16 regions, the blocked forward sweep's z chunk),
+ *             and the mean runs over the passes of one period,
+ *             round(2 pi / (2 omega tau)); the defect, lam and the norms stay
+ *             in FP64.
  *   tol <= 0  exactly max_it plain transposed iterations lam <- M^T lam + g
  *             from lam = 0 (check_every unused)
  *   grad_eps  device, 2*N doubles: (dJ/deps', dJ/deps'') per cell
