@@ -199,7 +199,7 @@ int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
  *             from lam = 0 (check_every unused)
  *   grad_eps  device, 2*N doubles: (dJ/deps', dJ/deps'') per cell
  *   J, iters (transposed sweeps run), rel_res  host, may be NULL
- * Needs a context created with grid.adjoint = 1 (compact storage); the
+ * Needs a context created with grid.adjoint = 1 (compact storage); the FP64
  * transposed sweep uses the fused tile and z chunk.  Synchronising. */
 int thiim_adjoint_grad(thiim_ctx *ctx, const double *weight, double tol, int max_it,
                        int check_every, double *grad_eps, double *J, int *iters,
