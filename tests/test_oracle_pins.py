@@ -396,3 +396,38 @@ def test_spectral_radius_of_the_iteration(oracle_lib):
     assert 1.0 <= ratio[3000] < 1.0 + 1e-3
     # an eigenvalue of modulus > 1 would hold the ratio above 1 at a constant
     assert ratio[3000] - 1.0 < 0.6 * (ratio[1000] - 1.0)
+
+
+def test_split_difference_of_symmetric_pairs_is_invisible(oracle_lib):
+    """The reading behind the pair-sum form of the complex64 inner sweeps:
+    where both parts of a split pair have identical coefficients (the z pairs
+    everywhere, the x and y pairs on planes without a PML term), moving a
+    value from one part to the other changes no physical field after an
+    iteration -- one iteration maps the pair's sum on its own and the other
+    field reads only sums.  On a PML plane the same move of an x pair is
+    visible (control)."""
+    pb = inputs.random_problem(7, 6, 14, seed=41, npml=3)
+    coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h)
+    g = inputs.rng(42)
+    shape = (12,) + pb.shape
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    ref = P(oracle.phi(coef, x))
+    nz = pb.shape[0]
+    hsym = np.asarray(pb.sig_h) == 0.0
+    esym = np.asarray(pb.sig_e) == 0.0
+    assert hsym.any() and esym.any() and not hsym.all() and not esym.all()
+    y = x.copy()
+    for c in range(6):
+        a, b = 2 * c, 2 * c + 1
+        sym = np.ones(nz, bool) if c in (2, 5) else (hsym if c < 3 else esym)
+        d = (g.standard_normal(pb.shape) + 1j * g.standard_normal(pb.shape)) * sym[:, None, None]
+        y[a] += d
+        y[b] -= d
+    out = P(oracle.phi(coef, y))
+    assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(ref)
+    # control: the same move of the H_x pair on a PML plane is seen
+    k = int(np.nonzero(~hsym)[0][0])
+    z = x.copy()
+    z[0, k] += 1.0
+    z[1, k] -= 1.0
+    assert np.linalg.norm(P(oracle.phi(coef, z)) - ref) > 1e-6 * np.linalg.norm(ref)
