@@ -50,7 +50,8 @@ extern "C" {
 #define THIIM_EINVAL (-1)    /* invalid argument */
 #define THIIM_ENOMEM (-2)    /* workspace too small */
 #define THIIM_EDEVICE (-3)   /* HIP runtime or device error */
-#define THIIM_EDIVERGED (-4) /* non-finite or growing residual */
+#define THIIM_EDIVERGED (-4) /* residual not finite, or grown 1e6-fold over the
+                              * smallest one the solve reached */
 #define THIIM_ENOTCONV (-5)  /* iteration limit reached before tolerance */
 
 #define THIIM_PERIODIC 0
@@ -162,7 +163,9 @@ int thiim_residual(thiim_ctx *ctx, double *rel_res);
  * half to each part: a MIXED solve determines the physical fields P x, not
  * how such a pair is split.
  * *iters (sweeps done, both precisions) and *rel_res may be NULL.
- * Synchronising; THIIM_ENOTCONV when max_it is reached first. */
+ * Synchronising; THIIM_ENOTCONV when max_it is reached first;
+ * THIIM_EDIVERGED when a residual is not finite or exceeds 1e6 times the
+ * smallest one reached so far (e.g. a medium with gain, eps'' < 0). */
 int thiim_solve(thiim_ctx *ctx, double tol, int max_it, int check_every,
                 int *iters, double *rel_res);
 

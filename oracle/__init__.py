@@ -10,7 +10,7 @@ is the seeded input generator, which holds none of the method's arithmetic.
 Contents
   * ``coeffs``    -- the 28 coefficient arrays from the material data
                      (Eq. 3-5 solved for the new value; C, ``thiim_oracle.c``)
-  * ``iterate``   -- n THIIM iterations, the 12 loop nests of Listings 1/2 (C)
+  * ``iterate``   -- n THIIM iterations, one loop nest per split component (C)
   * ``iterate_light`` -- the same without coefficient arrays (memory-light
                      mode for full-size grids; bit-identical)
   * ``residual``  -- ||P(Phi(x) - x)||_2 / ||P Phi(0)||_2 in FP64, P the sum

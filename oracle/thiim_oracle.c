@@ -17,9 +17,10 @@
  *   - Sec. I-A, Eq. (5): "back iteration" for cells with negative
  *     permittivity (only the E coefficients change).
  *   - Sec. I-A, Eq. (6) and (7): Berenger split field, 12 split components.
- *   - Sec. III, Listings 1 and 2: per-component loop nest over k, j, i, the
- *     interleaved (re, im) layout with x fastest, and the operation order of
- *     the complex update (22 flops with a source array, 20 without).
+ *   - Sec. III, Listings 1 and 2: one loop nest over k, j, i per split
+ *     component, the interleaved (re, im) layout with x fastest, the index
+ *     shift of each difference and the flop count of one update (22 with a
+ *     source array, 20 without).
  *   - Sec. II-B / Fig. 3: H depends on E at an offset of -1, E depends on H
  *     in the opposite (+1) direction.
  *
@@ -278,12 +279,19 @@ static int coef_at(const csrc_t *cs, int q, int k, long p, double *tr, double *t
 /* The 12 loop nests (Listings 1 and 2).                                   */
 /* ---------------------------------------------------------------------- */
 
-/* One component update over the whole domain, in the form of Listings 1/2:
- *   D  = G(a) - G(b) summed part by part, (a, b) chosen so that the update
- *        reads  F <- t F + Src - c D  (the listing always subtracts c D),
- *   H: backward difference, E: forward difference along the component axis.
- * With s the curl sign:  s c (G(p) - G(p-e)) = -c D  =>  D = -s (G(p) - G(p-e))
- * for H, and D = -s (G(p+e) - G(p)) for E. */
+/* One component update over the whole domain: Eq. (3) (E) or Eq. (4) (H)
+ * solved for the new value,
+ *     F(p) <- t(p) F(p) + Src(p) + s c(p) D(p),
+ * with D the difference of the driving component G = G1 + G2 (the sum of its
+ * two split parts) along the part's axis: the backward difference
+ * G(p) - G(p - e) for H, the forward difference G(p + e) - G(p) for E
+ * (Fig. 3: the two fields depend on each other in opposite directions); a
+ * neighbour outside the domain contributes 0, and s is the sign of that
+ * derivative in the curl.  Real arithmetic with one complex product per
+ * coefficient: D costs 6 flops (the two sums and their difference, real and
+ * imaginary parts), t F and c D 6 each, combining them 2 and adding Src 2
+ * more -- the 20 and 22 flops per update of the paper's count (Sec. III-A).
+ * Real and imaginary parts are formed in locals and stored together. */
 static void update_component(const grid_t *g, int q, double *F, const csrc_t *cs,
                              const double *G1, const double *G2)
 {
@@ -297,39 +305,29 @@ static void update_component(const grid_t *g, int q, double *F, const csrc_t *cs
             for (int ii = 0; ii < g->nx; ii++) {
                 long p = ((long)k * g->ny + j) * g->nx + ii;
                 long ps = nbr(g, k, j, ii, cm->axis, dir);
-                double g1p = G1[2 * p], g1pi = G1[2 * p + 1];
-                double g2p = G2[2 * p], g2pi = G2[2 * p + 1];
-                double g1s = 0.0, g1si = 0.0, g2s = 0.0, g2si = 0.0;
+                /* G at the cell and at its neighbour along the axis */
+                double gr = G1[2 * p] + G2[2 * p];
+                double gi = G1[2 * p + 1] + G2[2 * p + 1];
+                double nr = 0.0, ni = 0.0;
                 if (ps >= 0) {
-                    g1s = G1[2 * ps]; g1si = G1[2 * ps + 1];
-                    g2s = G2[2 * ps]; g2si = G2[2 * ps + 1];
+                    nr = G1[2 * ps] + G2[2 * ps];
+                    ni = G1[2 * ps + 1] + G2[2 * ps + 1];
                 }
-                /* operands (a, b) of D = G(a) - G(b) */
-                double a1, a1i, b1, b1i, a2, a2i, b2, b2i;
-                int pos_first; /* D = G(p) - G(shift) ? */
-                if (is_h) pos_first = (cm->sign < 0);  /* H: D = -s (G(p) - G(p-e)) */
-                else      pos_first = (cm->sign > 0);  /* E: D = -s (G(p+e) - G(p)) */
-                if (pos_first) {
-                    a1 = g1p; a1i = g1pi; b1 = g1s; b1i = g1si;
-                    a2 = g2p; a2i = g2pi; b2 = g2s; b2i = g2si;
-                } else {
-                    a1 = g1s; a1i = g1si; b1 = g1p; b1i = g1pi;
-                    a2 = g2s; a2i = g2si; b2 = g2p; b2i = g2pi;
-                }
-                double Re = a1 - b1 + a2 - b2;
-                double Im = a1i - b1i + a2i - b2i;
+                double dr = is_h ? gr - nr : nr - gr;
+                double di = is_h ? gi - ni : ni - gi;
                 double fr = F[2 * p], fi = F[2 * p + 1];
                 double tr, ti, cr, ci, sr = 0.0, si = 0.0;
                 int has_src = coef_at(cs, q, k, p, &tr, &ti, &cr, &ci, &sr, &si);
-                double t;
+                double tf_r = tr * fr - ti * fi, tf_i = tr * fi + ti * fr;
+                double cd_r = cr * dr - ci * di, cd_i = cr * di + ci * dr;
+                double new_r = cm->sign > 0 ? tf_r + cd_r : tf_r - cd_r;
+                double new_i = cm->sign > 0 ? tf_i + cd_i : tf_i - cd_i;
                 if (has_src) {
-                    t = fr * tr - fi * ti + sr - cr * Re + ci * Im;
-                    F[2 * p + 1] = fr * ti + fi * tr + si - cr * Im - ci * Re;
-                } else {
-                    t = fr * tr - fi * ti - cr * Re + ci * Im;
-                    F[2 * p + 1] = fr * ti + fi * tr - cr * Im - ci * Re;
+                    new_r = new_r + sr;
+                    new_i = new_i + si;
                 }
-                F[2 * p] = t;
+                F[2 * p] = new_r;
+                F[2 * p + 1] = new_i;
             }
         }
     }
@@ -481,7 +479,7 @@ int oracle_adjoint_iterate(int nx, int ny, int nz, int bcx, int bcy,
     return 0;
 }
 
-/* Flop count of one component update, as written above (Listings 1/2). */
+/* Flop count of one component update as written in update_component. */
 int oracle_flops_per_update(int has_src) { return has_src ? 22 : 20; }
 
 void oracle_set_threads(int n)

@@ -31,7 +31,7 @@ constexpr size_t kAlign = 256;
 constexpr int kResidBlocks = 1024;
 constexpr size_t kHeaderBytes = 4096;  // flag, reduction output
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Cells added to every array stride (17 x 256 bytes of complex128).  On a
 // power-of-two grid the arrays would otherwise all start at the same offset
@@ -487,6 +487,11 @@ namespace {
 // less than kWeak.
 constexpr double kWeak = 0.3;
 constexpr int kMaxInner = 1 << 15;
+// A solve is declared divergent when its residual exceeds kGrowth times the
+// smallest residual it has reached (a convergent THIIM iteration can grow
+// transiently, by far less; a medium with gain, eps'' < 0, grows without
+// bound).
+constexpr double kGrowth = 1e6;
 
 int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, double* rel_res) {
     const int other = 1 - c->cur;
@@ -497,7 +502,7 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
     const bool adaptive = inner <= 0;
     int m = adaptive ? (2 * Kp * T > 64 ? 2 * Kp * T : 64) : inner;
     int done = 0;
-    double r = INFINITY, prev = INFINITY;
+    double r = INFINITY, prev = INFINITY, best = INFINITY;
     for (;;) {
         // FP64: Phi(x) into the other buffer, r = Phi(x) - x (complex64 copy)
         hipError_t e = one_pass(c, c->cur, other);
@@ -512,11 +517,13 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
         if (e != hipSuccess) return hip_fail(e, "mixed: residual sync");
         done += 1;
         r = std::sqrt(host[0]) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
-        if (!std::isfinite(r)) {
+        if (!std::isfinite(r) || r > kGrowth * best) {
             if (iters) *iters = done;
             if (rel_res) *rel_res = r;
-            return fail(THIIM_EDIVERGED, "residual is not finite");
+            return fail(THIIM_EDIVERGED, std::isfinite(r) ? "residual grew 1e6-fold: diverging"
+                                                          : "residual is not finite");
         }
+        best = std::min(best, r);
         if (r <= tol || done >= max_it) break;
         if (adaptive && std::isfinite(prev) && r > kWeak * prev && m < kMaxInner) m *= 2;
         // complex64: d = r, then passes of d <- M d + r; the last Kp averaged
@@ -560,12 +567,16 @@ int thiim_solve(thiim_ctx* c, double tol, int max_it, int check_every, int* iter
     int done = 0;
     double r = INFINITY;
     int rc = thiim_residual(c, &r);
+    double best = r;
     while (rc == THIIM_OK && r > tol && done < max_it) {
         const int step = check_every < max_it - done ? check_every : max_it - done;
         rc = thiim_iterate(c, step);
         if (rc) break;
         done += step;
         rc = thiim_residual(c, &r);
+        if (rc == THIIM_OK && r > kGrowth * best)
+            rc = fail(THIIM_EDIVERGED, "residual grew 1e6-fold: diverging");
+        best = std::min(best, r);
     }
     if (iters) *iters = done;
     if (rel_res) *rel_res = r;
@@ -641,18 +652,21 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
         int Kp = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau));
         if (Kp < 1) Kp = 1;
         int m = check_every > 2 * Kp ? check_every : 2 * Kp;
-        double prev = INFINITY;
+        double prev = INFINITY, best = INFINITY;
         for (;;) {
             e = sweep(0, 1, c->gadj, false);
             if (e != hipSuccess) return hip_fail(e, "adjoint: sweep");
             ++done;
             rc = measure(0, 1, &r);
             if (rc) return rc;
-            if (!std::isfinite(r)) {
+            if (!std::isfinite(r) || r > kGrowth * best) {
                 if (iters) *iters = done;
                 if (rel_res) *rel_res = r;
-                return fail(THIIM_EDIVERGED, "adjoint residual is not finite");
+                return fail(THIIM_EDIVERGED, std::isfinite(r)
+                                                 ? "adjoint residual grew 1e6-fold: diverging"
+                                                 : "adjoint residual is not finite");
             }
+            best = std::min(best, r);
             if (r <= tol || done >= max_it) break;
             if (std::isfinite(prev) && r > 0.3 * prev && m < (1 << 15)) m *= 2;
             prev = r;
@@ -837,10 +851,12 @@ int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
     const int regions[3][2] = {{32, 16}, {64, 8}, {64, 6}};
     const int tiles[4][2] = {{64, 8}, {32, 8}, {64, 4}, {16, 16}};
     for (int zc : chunks) {
-        if (zc < 4 || zc > g.nz) continue;
+        // chunks of at least 4 planes; a grid of 2 or 3 planes is one chunk
+        if (zc > g.nz || (zc < 4 && zc != g.nz)) continue;
         for (auto& r : regions) all.push_back({THIIM_KERNEL_BLOCKED, r[0], r[1], zc, 0.0});
         for (auto& t : tiles) all.push_back({THIIM_KERNEL_FUSED, t[0], t[1], zc, 0.0});
     }
+    if (all.empty()) return fail(THIIM_EINVAL, "autotune: no sweep configuration fits the grid");
     for (auto& k : all) k.model_ms = model_ms(g, k, c->ncu);
     std::sort(all.begin(), all.end(),
               [](const Candidate& a, const Candidate& b) { return a.model_ms < b.model_ms; });
@@ -878,6 +894,7 @@ int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    if (best < 0) return fail(THIIM_EDEVICE, "autotune: no trial produced a timing");
     apply(c, keep[best]);
     if (out) {
         out->kernel = keep[best].kernel;
@@ -928,14 +945,16 @@ namespace {
 
 constexpr int kGraphIters = 64;  // iterations per captured graph (a multiple of 4)
 
-size_t batch_items_bytes(int n) {
+constexpr size_t batch_items_bytes(int n) {
     return align_up((size_t)2 * n * sizeof(thiim::BatchItem), kAlign);
 }
-size_t batch_items32_bytes(int n) {
+constexpr size_t batch_items32_bytes(int n) {
     return align_up((size_t)2 * n * sizeof(thiim::BatchItem32), kAlign);
 }
 // item arrays (both kinds), then the 8 counters of the device work queue
-size_t batch_bytes(int n) { return batch_items_bytes(n) + batch_items32_bytes(n) + kAlign; }
+constexpr size_t batch_bytes(int n) {
+    return batch_items_bytes(n) + batch_items32_bytes(n) + kAlign;
+}
 unsigned int* batch_queue(thiim_batch* b, int n) {
     return (unsigned int*)(b->ws + batch_items_bytes(n) + batch_items32_bytes(n));
 }
@@ -1124,7 +1143,7 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
         if (2 * Kp[i] * T[i] > m) m = 2 * Kp[i] * T[i];
     }
     if (m_user > 0) m = m_user;
-    std::vector<double> prev(n, INFINITY);
+    std::vector<double> prev(n, INFINITY), best(n, INFINITY);
     thiim::BatchItem32* base = (thiim::BatchItem32*)(b->ws + batch_items_bytes((int)n));
     struct G32 {
         int T;
@@ -1160,8 +1179,10 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
             thiim_ctx* c = b->ctx[i];
             done[i] += 1;
             r[i] = std::sqrt(host[2 * i]) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
-            if (!std::isfinite(r[i])) diverged = true;
-            if (!std::isfinite(r[i]) || r[i] <= tol || done[i] >= max_it) {
+            const bool grew = !std::isfinite(r[i]) || r[i] > kGrowth * best[i];
+            if (grew) diverged = true;
+            best[i] = std::min(best[i], r[i]);
+            if (grew || r[i] <= tol || done[i] >= max_it) {
                 b->active[i] = 0;
                 rebuild32 = true;
                 continue;
@@ -1291,15 +1312,11 @@ int thiim_batch_workspace_bytes(int n, size_t* bytes) {
     return THIIM_OK;
 }
 
-int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t workspace_bytes,
-                       thiim_batch** out) {
-    if (!out) return fail(THIIM_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!ctxs || n < 1) return fail(THIIM_EINVAL, "need n >= 1 contexts");
-    if (!workspace || (uintptr_t)workspace % kAlign)
-        return fail(THIIM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
-    if (workspace_bytes < batch_bytes(n))
-        return fail(THIIM_ENOMEM, "workspace smaller than thiim_batch_workspace_bytes()");
+}  // extern "C"
+
+namespace {
+
+int check_batch_contexts(thiim_ctx* const* ctxs, int n) {
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return fail(THIIM_EINVAL, "a context is NULL");
         if (!ctxs[i]->cv.compact) return fail(THIIM_EINVAL, "batches need the compact storage");
@@ -1308,12 +1325,16 @@ int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t wo
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(THIIM_EINVAL, "a context appears twice");
     }
+    return THIIM_OK;
+}
+
+int make_batch(thiim_ctx* const* ctxs, int n, char* ws, size_t ws_bytes, thiim_batch** out) {
     thiim_batch* b = new (std::nothrow) thiim_batch();
     if (!b) return fail(THIIM_EINVAL, "out of host memory");
     b->ctx.assign(ctxs, ctxs + n);
     b->stream = ctxs[0]->stream;
-    b->ws = (char*)workspace;
-    b->ws_bytes = workspace_bytes;
+    b->ws = ws;
+    b->ws_bytes = ws_bytes;
     b->queue = batch_queue(b, n);
     b->ncu = ctxs[0]->ncu;
     b->active.assign(n, 1);
@@ -1323,6 +1344,24 @@ int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t wo
     b->graph_iters = kGraphIters;
     *out = b;
     return THIIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t workspace_bytes,
+                       thiim_batch** out) {
+    if (!out) return fail(THIIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(THIIM_EINVAL, "need n >= 1 contexts");
+    if (!workspace || (uintptr_t)workspace % kAlign)
+        return fail(THIIM_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < batch_bytes(n))
+        return fail(THIIM_ENOMEM, "workspace smaller than thiim_batch_workspace_bytes()");
+    int rc = check_batch_contexts(ctxs, n);
+    if (rc) return rc;
+    return make_batch(ctxs, n, (char*)workspace, workspace_bytes, out);
 }
 
 int thiim_batch_iterate(thiim_batch* b, int n) {
@@ -1348,7 +1387,7 @@ int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, i
     const size_t n = b->ctx.size();
     std::fill(b->active.begin(), b->active.end(), 1);
     b->dirty = true;
-    std::vector<double> r(n, INFINITY);
+    std::vector<double> r(n, INFINITY), best(n, INFINITY);
     std::vector<int> done(n, 0);
     int step_done = 0, rc = THIIM_OK;
     bool diverged = false;
@@ -1366,8 +1405,10 @@ int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, i
             if (!b->active[i]) continue;
             r[i] = now[i];
             done[i] = step_done;
-            if (!std::isfinite(r[i])) diverged = true;
-            if (!std::isfinite(r[i]) || r[i] <= tol) {
+            const bool grew = !std::isfinite(r[i]) || r[i] > kGrowth * best[i];
+            if (grew) diverged = true;
+            best[i] = std::min(best[i], r[i]);
+            if (grew || r[i] <= tol) {
                 b->active[i] = 0;
                 b->dirty = true;
             } else {
@@ -1387,7 +1428,8 @@ int thiim_batch_solve(thiim_batch* b, double tol, int max_it, int check_every, i
         if (rel_res) rel_res[i] = r[i];
     }
     if (rc) return rc;
-    if (diverged) return fail(THIIM_EDIVERGED, "batch: a residual is not finite");
+    if (diverged)
+        return fail(THIIM_EDIVERGED, "batch: a residual is not finite or grew 1e6-fold");
     for (size_t i = 0; i < n; ++i)
         if (!(r[i] <= tol)) return fail(THIIM_ENOTCONV, "batch: iteration limit reached");
     return THIIM_OK;
@@ -1462,6 +1504,7 @@ int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    if (best < 0) return fail(THIIM_EDEVICE, "batch autotune: no trial produced a timing");
     apply_all(cands[best]);
     if (out) {
         out->kernel = cands[best].kernel;

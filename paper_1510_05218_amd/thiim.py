@@ -288,8 +288,8 @@ class Solver:
         self.ws_bytes = thiim_workspace_bytes(self.grid)
         # allocated on the stream the library runs on, so that torch's caching
         # allocator never hands the memory to another stream while kernels of
-        # this context may still use it
-        with torch.cuda.stream(self.stream):
+        # this context may still use it (and after the caller's pending work)
+        with self._lib_stream():
             self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
             eps = self._to_dev(problem.eps)
             srcs = [self._to_dev(problem.sources[k]) if k in problem.sources else None
@@ -329,12 +329,22 @@ class Solver:
         """Chooses this context's sweep configuration (thiim_autotune)."""
         return thiim_autotune(self.ctx, trial_iters).as_dict()
 
+    def _lib_stream(self):
+        """Context for torch work whose results the library reads or writes:
+        the library's stream first waits for the caller's current stream (so
+        inputs produced there are complete), then the conversions and
+        allocations run on the library's stream, ordered before the C call."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        return self.torch.cuda.stream(self.stream)
+
     def adjoint_grad(self, weight, tol=1e-10, max_it=100000, check_every=50):
         """Gradient of J = sum w eps'' |E|^2 at the current state.  Returns
         (status, J, grad, iterations, rel_res) with grad a complex128 tensor
         (nz, ny, nx) holding dJ/deps' + 1j dJ/deps''."""
-        w = self._to_dev_real(weight)
-        grad = self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+        with self._lib_stream():
+            w = self._to_dev_real(weight)
+            grad = self.torch.empty(self.shape, dtype=self.torch.complex128,
+                                    device=self.device)
         rc, J, it, r = thiim_adjoint_grad(self.ctx, w.data_ptr(), tol, max_it, check_every,
                                           grad.data_ptr())
         return rc, J, grad, it, r
@@ -349,20 +359,23 @@ class Solver:
 
     def fields(self):
         """The 12 split fields, complex128 tensor (12, nz, ny, nx) on the GPU."""
-        out = self.torch.empty((12,) + self.shape, dtype=self.torch.complex128,
-                               device=self.device)
+        with self._lib_stream():
+            out = self.torch.empty((12,) + self.shape, dtype=self.torch.complex128,
+                                   device=self.device)
         thiim_get_fields(self.ctx, out.data_ptr())
         return out
 
     def set_fields(self, x):
-        x = x.to(self.device, self.torch.complex128).contiguous()
+        with self._lib_stream():
+            x = x.to(self.device, self.torch.complex128).contiguous()
         assert tuple(x.shape) == (12,) + self.shape
         thiim_set_fields(self.ctx, x.data_ptr())
         self.stream.synchronize()
 
     def coeffs(self):
-        out = self.torch.empty((28,) + self.shape, dtype=self.torch.complex128,
-                               device=self.device)
+        with self._lib_stream():
+            out = self.torch.empty((28,) + self.shape, dtype=self.torch.complex128,
+                                   device=self.device)
         thiim_get_coeffs(self.ctx, out.data_ptr())
         return out
 

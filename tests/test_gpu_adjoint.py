@@ -11,7 +11,11 @@ torch.autograd interface.
     pinned against finite differences of the direct solve);
   * central finite differences (h = 1e-6) of J computed by the GPU solver on
     16 cells of the middle layer, every solve run to the same iteration count
-    from x0 = 0, within 1e-5 of the largest gradient entry;
+    from x0 = 0, within 1e-5 of the largest gradient entry -- on a small grid
+    and on the 128 x 128 x 256 gradient configuration itself;
+  * one averaged correction of the mixed-precision adjoint (the complex64
+    temporally blocked transposed sweep) against the mean of the oracle's
+    transposed iterates over the same window, at a complex64 tolerance;
   * torch.autograd.gradcheck of the differentiable absorption functional.
 """
 import numpy as np
@@ -234,3 +238,112 @@ def test_adjoint_on_mixed_context_matches_fp64():
         s.close()
     scale = np.abs(grads[0]).max()
     assert np.abs(grads[1] - grads[0]).max() <= 1e-8 * scale
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 1)])
+def test_adjoint32_blocked_one_correction_matches_oracle(bcx, bcy):
+    """On a mixed-precision context, tol > 0 and max_it = 1 + m stop the
+    adjoint after exactly one defect correction: one FP64 transposed sweep
+    from lam = 0 gives r = g, then P passes of the complex64 blocked
+    transposed sweep (two sweeps each) run d <- M^T d + g from d = g, and lam
+    is the mean of d after the last Kq passes.  After j sweeps d equals the
+    plain transposed iterate lam_{j+1}, so the oracle's lam is the mean of
+    lam_{2p+3} over those passes p; both gradients are formed from the same
+    forward state.  Complex64 tolerance: 1e-5 of the largest entry."""
+    _require_gpu()
+    print(f"[adjoint32 blocked] bc=({bcx},{bcy})", flush=True)
+    pb = _with_back_cells(inputs.random_problem(37, 19, 14, seed=61, bcx=bcx, bcy=bcy), 62)
+    w = inputs.rng(63).uniform(0, 1, pb.shape)
+    nf, m = 40, 100
+    s = thiim.Solver(pb, storage="compact", precision="mixed", adjoint=True, kernel="fused")
+    s.iterate(nf)
+    x = s.fields().cpu().numpy()
+    rc, J, grad, it, _ = s.adjoint_grad(w, tol=1e-30, max_it=1 + m, check_every=m)
+    assert rc == thiim.THIIM_ENOTCONV, rc
+    grad = grad.cpu().numpy()
+    s.close()
+    wt = pb.omega * pb.tau
+    Kp = max(1, int(round(2 * np.pi / wt)))
+    Kq = max(1, int(round(2 * np.pi / (wt * 2))))
+    mm = max(m, 2 * Kp)
+    P = max((mm + 1) // 2, Kq)
+    coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h)
+    xo = oracle.iterate(coef, oracle.zero_fields(pb.shape), nf, bcx, bcy)
+    assert np.linalg.norm(x - xo) <= 1e-12 * np.linalg.norm(xo)
+    g = adjoint.adjoint_source(pb.eps, xo, w)
+    lam = oracle.adjoint_iterate(coef, np.zeros_like(g), g, 2 * (P - Kq) + 3, bcx, bcy)
+    acc = lam.copy()
+    for _ in range(Kq - 1):
+        lam = oracle.adjoint_iterate(coef, lam, g, 2, bcx, bcy)
+        acc += lam
+    acc /= Kq
+    go = adjoint.gradient(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h,
+                          xo, acc, w, bcx, bcy)
+    scale = np.abs(go).max()
+    err = max(np.abs(grad.real - go.real).max(), np.abs(grad.imag - go.imag).max())
+    print(f"[adjoint32 blocked] max error {err / scale:.2e} of the largest entry", flush=True)
+    assert err <= 1e-5 * scale
+
+
+def test_adjoint_fd_16_cells_128x128x256():
+    """The gradient configuration at its full size (128 x 128 x 256 textured
+    stack, J over the middle layer, forward and adjoint to 1e-10), checked
+    cell by cell: for 16 seeded middle-layer cells and both eps' and eps'',
+    the central difference (h = 1e-6) of J against the adjoint gradient.
+    Every perturbed forward solve runs the unperturbed sweep schedule (fixed
+    inner count, stopped at the same sweep count), so the truncation errors
+    of the two sides correlate.  J(eps + h) - J(eps - h) is formed cell by
+    cell from the two physical E fields,
+        w eps''_+ Re((E_+ - E_-) conj(E_+ + E_-)) + w (eps''_+ - eps''_-) |E_-|^2,
+    rather than as the difference of two sums of 1.3 million terms, whose
+    rounding would exceed the single-cell signal."""
+    _require_gpu()
+    pb = inputs.solar_cell(128, 128, 256, seed=20, npml=6, loss_range=(0.1, 0.5))
+    mid = pb.layers[1][2]
+    w = (pb.eps == mid).astype(np.float64)
+    m = 2000
+    kw = dict(storage="compact", precision="mixed", t_block=3, adjoint=True)
+    s = thiim.Solver(pb, **kw)
+    rc, n_sw, r = s.solve(1e-10, 2000000, m)
+    assert rc == thiim.THIIM_OK, (n_sw, r)
+    rc, J0, grad, ait, ar = s.adjoint_grad(w, tol=1e-10, max_it=2000000, check_every=m)
+    assert rc == thiim.THIIM_OK, (ait, ar)
+    print(f"[adjoint fd 128x128x256] forward {n_sw}, adjoint {ait} sweeps", flush=True)
+    grad = grad.cpu().numpy()
+    s.close()
+    scale = np.abs(grad).max()
+    wd = torch.from_numpy(w).cuda()
+    g = inputs.rng(26)
+    ks, js, is_ = np.nonzero(w)
+    pick = g.choice(len(ks), size=16, replace=False)
+    cells = [(int(ks[i]), int(js[i]), int(is_[i])) for i in pick]
+    hfd = 1e-6
+
+    def E_at(eps):
+        p = inputs.Problem(**{**pb.__dict__, "eps": eps})
+        sp = thiim.Solver(p, **kw)
+        sp.solve(1e-30, n_sw, m)  # the unperturbed schedule, stopped at n_sw sweeps
+        x = sp.fields()
+        sp.close()
+        return x[6::2] + x[7::2]
+
+    worst = 0.0
+    for n, c in enumerate(cells):
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            ep, em = pb.eps.copy(), pb.eps.copy()
+            ep[c] += hfd * unit
+            em[c] -= hfd * unit
+            Ep, Em = E_at(ep), E_at(em)
+            dE2 = torch.sum(((Ep - Em) * torch.conj(Ep + Em)).real, dim=0)
+            e2m = torch.sum((Em * torch.conj(Em)).real, dim=0)
+            epp_p = torch.from_numpy(ep.imag.copy()).cuda()
+            epp_m = torch.from_numpy(em.imag.copy()).cuda()
+            dJ = float(torch.sum(wd * epp_p * dE2) + torch.sum(wd * (epp_p - epp_m) * e2m))
+            del Ep, Em, dE2, e2m
+            fd = dJ / (2 * hfd)
+            an = grad[c].real if part == "re" else grad[c].imag
+            worst = max(worst, abs(fd - an) / scale)
+            print(f"[adjoint fd 128x128x256] cell {n} {c} d/deps{part}: fd {fd:.9e} "
+                  f"adjoint {an:.9e}", flush=True)
+            assert abs(fd - an) <= 1e-5 * scale, (c, part, fd, an, scale)
+    print(f"[adjoint fd 128x128x256] worst {worst:.2e} of the largest entry", flush=True)

@@ -2,8 +2,11 @@
 
 Tolerances: coefficient arrays elementwise 2e-15 relative (both sides round
 the same closed forms in different operation orders); iterates 1e-12 in the
-relative 2-norm over all 12 split arrays; the naive, fused and blocked sweeps
-bit-identical to each other (same per-element operation sequence)."""
+relative 2-norm over all 12 split arrays and, part by part, every value
+within 1e-12 of the largest field magnitude (so an error confined to one
+part or a few cells cannot hide in the global norm); the naive, fused and
+blocked sweeps bit-identical to each other (same per-element operation
+sequence)."""
 import numpy as np
 import pytest
 
@@ -41,6 +44,19 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def _assert_parity(xg, xo, tol=1e-12, what=None):
+    """GPU iterate against the oracle's: relative 2-norm over all parts, and
+    the largest absolute error of each of the 12 parts against the largest
+    magnitude of the whole field."""
+    xg = np.asarray(xg.cpu().numpy() if hasattr(xg, "cpu") else xg)
+    xo = np.asarray(xo)
+    assert _rel(xg, xo) < tol, what
+    scale = float(np.max(np.abs(xo)))
+    for q in range(12):
+        err = float(np.max(np.abs(xg[q] - xo[q])))
+        assert err <= tol * scale, (what, q, err, scale)
+
+
 def _with_back_cells(pb, seed):
     g = inputs.rng(seed)
     mask = g.random(pb.eps.shape) < 0.1
@@ -70,7 +86,7 @@ def test_c1_layered_textured_200_iterations(kernel, storage):
     pb = inputs.solar_cell(24, 24, 36, seed=1, npml=6)
     _, xo = _oracle_run(pb, 200)
     _, xg = _gpu_run(pb, 200, kernel=kernel, storage=storage)
-    assert _rel(xg.cpu().numpy(), xo) < 1e-12
+    _assert_parity(xg, xo)
 
 
 def test_128cubed_random_media_20_iterations():
@@ -82,7 +98,7 @@ def test_128cubed_random_media_20_iterations():
     pb = _with_back_cells(inputs.random_problem(128, 128, 128, seed=29, npml=6), 30)
     _, xo = _oracle_run(pb, 20)
     _, xn = _gpu_run(pb, 20, kernel="naive", storage="full")
-    assert _rel(xn.cpu().numpy(), xo) < 1e-12
+    _assert_parity(xn, xo)
     for kernel, storage in (("fused", "compact"), ("blocked", "compact"), ("blocked", "full")):
         s, x = _gpu_run(pb, 20, kernel=kernel, storage=storage)
         s.close()
@@ -97,7 +113,7 @@ def test_random_ragged_problem(bcx, bcy):
     pb = _with_back_cells(inputs.random_problem(37, 29, 23, seed=11, bcx=bcx, bcy=bcy), 12)
     _, xo = _oracle_run(pb, 25)
     _, xn = _gpu_run(pb, 25, kernel="naive")
-    assert _rel(xn.cpu().numpy(), xo) < 1e-12
+    _assert_parity(xn, xo)
     for tile in [(64, 8), (32, 8), (64, 4), (16, 16)]:
         for zc in (0, 5, 64):
             _, xf = _gpu_run(pb, 25, kernel="fused", tile=tile, z_chunk=zc)
@@ -128,7 +144,7 @@ def test_tiny_grids_wrap_many_times():
         _, xf = _gpu_run(pb, 15, kernel="fused")
         _, xb = _gpu_run(pb, 15, kernel="blocked")
         _, xbc = _gpu_run(pb, 15, kernel="blocked", storage="compact")
-        assert _rel(xn.cpu().numpy(), xo) < 1e-12
+        _assert_parity(xn, xo)
         assert torch.equal(xf, xn)
         assert torch.equal(xb, xn)
         assert torch.equal(xbc, xn)
@@ -150,7 +166,7 @@ def test_smallest_grid_and_zero_iterations():
             for storage in ("full", "compact"):
                 s, xg = _gpu_run(pb, 30, kernel=kernel, storage=storage)
                 s.close()
-                assert _rel(xg.cpu().numpy(), xo) < 1e-12, (bcx, kernel, storage)
+                _assert_parity(xg, xo, what=(bcx, kernel, storage))
     pb = inputs.solar_cell(24, 24, 36, seed=1, npml=6)
     s = thiim.Solver(pb, kernel="blocked", storage="compact")
     s.iterate(0)
@@ -346,4 +362,4 @@ def test_invalid_material_rejected_at_create():
     s, x = _gpu_run(pb, 5, kernel="blocked", storage="compact")
     s.close()
     _, xo = _oracle_run(pb, 5)
-    assert _rel(x.cpu().numpy(), xo) < 1e-12
+    _assert_parity(x, xo)

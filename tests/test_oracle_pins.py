@@ -133,24 +133,40 @@ def test_yee_dispersion(oracle_lib, kind, pol, axis, m):
 
 
 # --------------------------------------------------------------------------
-# Listings 1 and 2 (operation order, bitwise)
+# Component updates: index shifts and signs fixed by Listings 1 and 2
 # --------------------------------------------------------------------------
-def _listing_update(F, t, c, src, g1, g2, a_shift, b_shift):
-    """Literal form of Listings 1/2 in numpy (no FMA): D = G1(a) - G1(b) +
-    G2(a) - G2(b) evaluated left to right, then t F + Src - c D."""
-    Re = g1[a_shift].real - g1[b_shift].real + g2[a_shift].real - g2[b_shift].real
-    Im = g1[a_shift].imag - g1[b_shift].imag + g2[a_shift].imag - g2[b_shift].imag
-    fr, fi = F.real, F.imag
+def _update_ref(F, t, c, src, g1, g2, sign, here, nbr, backward):
+    """F <- t F + Src + s c D in explicit real arithmetic (one rounding per
+    numpy operation, so no fused multiply-add): G = G1 + G2 at the cell
+    (index ``here``) and at its neighbour (``nbr``); D = G(p) - G(p - e) for a
+    backward (H) and G(p + e) - G(p) for a forward (E) difference."""
+    gr = g1[here].real + g2[here].real
+    gi = g1[here].imag + g2[here].imag
+    nr = g1[nbr].real + g2[nbr].real
+    ni = g1[nbr].imag + g2[nbr].imag
+    dr, di = (gr - nr, gi - ni) if backward else (nr - gr, ni - gi)
+    tfr = t.real * F.real - t.imag * F.imag
+    tfi = t.real * F.imag + t.imag * F.real
+    cdr = c.real * dr - c.imag * di
+    cdi = c.real * di + c.imag * dr
+    re = tfr + cdr if sign > 0 else tfr - cdr
+    im = tfi + cdi if sign > 0 else tfi - cdi
     if src is not None:
-        tt = fr * t.real - fi * t.imag + src.real - c.real * Re + c.imag * Im
-        im = fr * t.imag + fi * t.real + src.imag - c.real * Im - c.imag * Re
-    else:
-        tt = fr * t.real - fi * t.imag - c.real * Re + c.imag * Im
-        im = fr * t.imag + fi * t.real - c.real * Im - c.imag * Re
-    return tt + 1j * im
+        re = re + src.real
+        im = im + src.imag
+    return re + 1j * im
 
 
-def test_listing1_and_listing2_bitwise(oracle_lib):
+def test_listing_components_bitwise(oracle_lib):
+    """The two components the paper prints fix their shifts, signs and
+    source arrays: H_yx (Listing 1) is driven by E_x = E_xy + E_xz through the
+    difference over the outer (z) dimension, E_x(k) - E_x(k-1), subtracted
+    after scaling by c, with the source array SrcHy; H_zx (Listing 2) by E_x
+    through the middle (y) dimension, E_x(j) - E_x(j-1) added after scaling,
+    without a source.  The E parts with the same shapes use the forward
+    difference and read the new H (Fig. 3).  Checked bit for bit against the
+    update evaluated in explicit real arithmetic on random data (interior
+    cells, where no wrap or wall is involved)."""
     g = inputs.rng(11)
     nz, ny, nx = 5, 6, 7
 
@@ -160,25 +176,23 @@ def test_listing1_and_listing2_bitwise(oracle_lib):
     coef = crand(28, nz, ny, nx)
     x0 = crand(12, nz, ny, nx)
     x1 = oracle.iterate(coef, x0.copy(), 1)
-    inner = (slice(None),) * 3
-    # Listing 1: H_yx (index 2), outer-dimension shift by -Nx*Ny, Src = SrcHy (25)
-    ref = _listing_update(x0[2][1:], coef[2][1:], coef[14][1:], coef[25][1:],
-                          x0[6], x0[7], (slice(1, None),) + inner[1:],
-                          (slice(0, -1),) + inner[1:])
+    k_hi, k_lo = (slice(1, None),), (slice(0, -1),)
+    j_hi, j_lo = (slice(None), slice(1, None)), (slice(None), slice(0, -1))
+    # H_yx (2): -c (E_x(k) - E_x(k-1)) + SrcHy (array 25)
+    ref = _update_ref(x0[2][1:], coef[2][1:], coef[14][1:], coef[25][1:], x0[6], x0[7],
+                      -1, k_hi, k_lo, True)
     assert np.array_equal(x1[2][1:], ref)
-    # Listing 2: H_zx (index 4), middle-dimension shift by -Nx, no Src
-    ref = _listing_update(x0[4][:, 1:], coef[4][:, 1:], coef[16][:, 1:], None,
-                          x0[6], x0[7], (slice(None), slice(0, -1)),
-                          (slice(None), slice(1, None)))
+    # H_zx (4): +c (E_x(j) - E_x(j-1)), no source
+    ref = _update_ref(x0[4][:, 1:], coef[4][:, 1:], coef[16][:, 1:], None, x0[6], x0[7],
+                      +1, j_hi, j_lo, True)
     assert np.array_equal(x1[4][:, 1:], ref)
-    # E_xy (index 6): opposite (+1) outer shift, reads the new H_y = H_yx + H_yz
-    ref = _listing_update(x0[6][:-1], coef[6][:-1], coef[18][:-1], coef[26][:-1],
-                          x1[2], x1[3], (slice(1, None),), (slice(0, -1),))
+    # E_xy (6): -c (H_y(k+1) - H_y(k)) with the new H_y = H_yx + H_yz, SrcEx (26)
+    ref = _update_ref(x0[6][:-1], coef[6][:-1], coef[18][:-1], coef[26][:-1], x1[2], x1[3],
+                      -1, k_lo, k_hi, False)
     assert np.array_equal(x1[6][:-1], ref)
-    # E_xz (index 7): +1 middle shift of H_z, curl sign +1 -> D = G(p) - G(p+e)
-    ref = _listing_update(x0[7][:, :-1], coef[7][:, :-1], coef[19][:, :-1], None,
-                          x1[4], x1[5], (slice(None), slice(0, -1)),
-                          (slice(None), slice(1, None)))
+    # E_xz (7): +c (H_z(j+1) - H_z(j)), no source
+    ref = _update_ref(x0[7][:, :-1], coef[7][:, :-1], coef[19][:, :-1], None, x1[4], x1[5],
+                      +1, j_lo, j_hi, False)
     assert np.array_equal(x1[7][:, :-1], ref)
 
 

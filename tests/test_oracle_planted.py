@@ -30,9 +30,9 @@ MUTATIONS = {
     "phase_H": ("*t = conj(ph2) / d;", "*t = ph2 / d;"),
     # e^{-iwt/2} dropped from c_E
     "cE_phase": ("*c = (tau / (eps * h)) * conj(ph2) / d;", "*c = (tau / (eps * h)) / d;"),
-    # real and imaginary parts of c swapped in the listing arithmetic
-    "swap_c": ("F[2 * p + 1] = fr * ti + fi * tr + si - cr * Im - ci * Re;",
-               "F[2 * p + 1] = fr * ti + fi * tr + si - ci * Im - cr * Re;"),
+    # real and imaginary parts of c swapped in the complex product c D
+    "swap_c": ("double cd_r = cr * dr - ci * di, cd_i = cr * di + ci * dr;",
+               "double cd_r = ci * dr - cr * di, cd_i = ci * di + cr * dr;"),
     # PML conductivity of H applied to the wrong components
     "pml_axis": ("double sst = (cq->axis == 2) ? sig_h[k] : 0.0;",
                  "double sst = (cq->axis == 1) ? sig_h[k] : 0.0;"),
