@@ -251,6 +251,21 @@ int thiim_batch_workspace_bytes(int n, size_t *bytes);
 int thiim_batch_create(thiim_ctx *const *ctxs, int n, void *workspace,
                        size_t workspace_bytes, thiim_batch **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * batch as thiim_batch_create without a workspace.  Its item tables and
+ * work-queue counters live in a static device array of the library (256 KiB
+ * per device, held until the process ends), so n <= 128 (THIIM_EINVAL
+ * beyond).  All contexts must be on one device; the first call on a device
+ * looks up the array's address there.  One such batch per device at a time:
+ * the array keeps the last batch's tables (re-uploaded by every new batch,
+ * the queue counters reset before every pass), so a second call on a device
+ * whose static batch is still alive fails with THIIM_EINVAL; destroy the
+ * first (thiim_batch_destroy, which then waits for the batch's stream).
+ * Calls on one batch from several threads at once race, as for any batch.
+ * No device memory is allocated or freed. */
+int thiim_batch_create_static(thiim_ctx *const *ctxs, int n, thiim_batch **out);
+
 /* n iterations of every context.  Asynchronous (uploads the item tables, a
  * synchronising copy, when the batch changed). */
 int thiim_batch_iterate(thiim_batch *batch, int n);

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -939,6 +940,7 @@ struct thiim_batch {
     hipGraphExec_t exec;
     int graph_iters;
     std::vector<int> graph_par;
+    int static_dev;  // device whose static scratch this batch holds, or -1
 };
 
 namespace {
@@ -1328,7 +1330,8 @@ int check_batch_contexts(thiim_ctx* const* ctxs, int n) {
     return THIIM_OK;
 }
 
-int make_batch(thiim_ctx* const* ctxs, int n, char* ws, size_t ws_bytes, thiim_batch** out) {
+int make_batch(thiim_ctx* const* ctxs, int n, char* ws, size_t ws_bytes, int static_dev,
+               thiim_batch** out) {
     thiim_batch* b = new (std::nothrow) thiim_batch();
     if (!b) return fail(THIIM_EINVAL, "out of host memory");
     b->ctx.assign(ctxs, ctxs + n);
@@ -1342,9 +1345,37 @@ int make_batch(thiim_ctx* const* ctxs, int n, char* ws, size_t ws_bytes, thiim_b
     b->graph = nullptr;
     b->exec = nullptr;
     b->graph_iters = kGraphIters;
+    b->static_dev = static_dev;
     *out = b;
     return THIIM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Allocation-free batches.  The item tables and queue counters of a batch
+// created by thiim_batch_create_static live in `scratch`, a file-scope
+// device array of kStaticBatchBytes (room for kStaticBatchMax problems); each
+// device holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, so its device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that
+// address is used (item uploads, kernel arguments).  One static batch per
+// device at a time: the scratch keeps the last batch's tables, and a second
+// batch would overwrite them, so creation is refused while one is alive.
+// ---------------------------------------------------------------------------
+constexpr int kStaticBatchMax = 128;
+constexpr size_t kStaticBatchBytes = 256 * 1024;
+static_assert(batch_bytes(kStaticBatchMax) <= kStaticBatchBytes,
+              "static batch scratch too small for kStaticBatchMax problems");
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticBatchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+bool g_scratch_busy[kMaxDevices];  // a static batch holds the device's scratch
 
 }  // namespace
 
@@ -1361,7 +1392,43 @@ int thiim_batch_create(thiim_ctx* const* ctxs, int n, void* workspace, size_t wo
         return fail(THIIM_ENOMEM, "workspace smaller than thiim_batch_workspace_bytes()");
     int rc = check_batch_contexts(ctxs, n);
     if (rc) return rc;
-    return make_batch(ctxs, n, (char*)workspace, workspace_bytes, out);
+    return make_batch(ctxs, n, (char*)workspace, workspace_bytes, -1, out);
+}
+
+int thiim_batch_create_static(thiim_ctx* const* ctxs, int n, thiim_batch** out) {
+    if (!out) return fail(THIIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return fail(THIIM_EINVAL, "need n >= 1 contexts");
+    if (n > kStaticBatchMax)
+        return fail(THIIM_EINVAL, "thiim_batch_create_static: at most " +
+                                      std::to_string(kStaticBatchMax) +
+                                      " problems (static scratch); use thiim_batch_create");
+    int rc = check_batch_contexts(ctxs, n);
+    if (rc) return rc;
+    const int dev = ctxs[0]->device;
+    for (int i = 1; i < n; ++i)
+        if (ctxs[i]->device != dev)
+            return fail(THIIM_EINVAL, "all contexts of a batch must be on one device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(THIIM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_busy[dev])
+        return fail(THIIM_EINVAL, "the static batch scratch of this device is held by another "
+                                  "batch (destroy it first)");
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "thiim_batch_create_static: scratch address");
+        if (!ptr || (uintptr_t)ptr % kAlign)
+            return fail(THIIM_EDEVICE, "thiim_batch_create_static: unaligned scratch");
+        g_scratch_ptr[dev] = (char*)ptr;
+    }
+    rc = make_batch(ctxs, n, g_scratch_ptr[dev], kStaticBatchBytes, dev, out);
+    if (rc == THIIM_OK) g_scratch_busy[dev] = true;
+    return rc;
 }
 
 int thiim_batch_iterate(thiim_batch* b, int n) {
@@ -1523,6 +1590,13 @@ int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
 void thiim_batch_destroy(thiim_batch* b) {
     if (!b) return;
     drop_graph(b);
+    if (b->static_dev >= 0) {
+        // no kernel of this batch may still read the tables when the next
+        // static batch overwrites them
+        (void)hipStreamSynchronize(b->stream);
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        g_scratch_busy[b->static_dev] = false;
+    }
     delete b;
 }
 

@@ -34,6 +34,7 @@ SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_adjoint_grad", "thiim_autotune", "thiim_batch_workspace_bytes",
            "thiim_batch_create", "thiim_batch_iterate", "thiim_batch_residual",
            "thiim_batch_solve", "thiim_batch_autotune", "thiim_batch_destroy",
+           "thiim_batch_create_static",
            "thiim_destroy",
            "thiim_last_error", "thiim_status_str")
 
@@ -99,6 +100,7 @@ def lib():
         L.thiim_autotune.argtypes = [vp, i, P(Tuning)]
         L.thiim_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
         L.thiim_batch_create.argtypes = [P(vp), i, vp, ctypes.c_size_t, P(vp)]
+        L.thiim_batch_create_static.argtypes = [P(vp), i, P(vp)]
         L.thiim_batch_iterate.argtypes = [vp, i]
         L.thiim_batch_residual.argtypes = [vp, P(d)]
         L.thiim_batch_solve.argtypes = [vp, d, i, i, P(i), P(d)]
@@ -213,6 +215,16 @@ def thiim_batch_create(ctxs, workspace_ptr: int, workspace_bytes: int):
     out = ctypes.c_void_p()
     _check(lib().thiim_batch_create(arr, len(ctxs), ctypes.c_void_p(workspace_ptr),
                                     workspace_bytes, ctypes.byref(out)))
+    return out
+
+
+def thiim_batch_create_static(ctxs):
+    """The allocation-free batch: item tables and queue counters in the
+    library's static device scratch (at most 128 problems, one such batch per
+    device at a time)."""
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    out = ctypes.c_void_p()
+    _check(lib().thiim_batch_create_static(arr, len(ctxs), ctypes.byref(out)))
     return out
 
 
