@@ -22,10 +22,13 @@ summary when it was taken on the current kernel sources, else null.
 
 Context entries (not part of the timed step): the other sweep variants, the
 transposed (adjoint) sweep at the same size, time to solution at relative
-residual 1e-8 for the plain FP64 iteration and the mixed-precision solver on
-a 128 x 128 x 256 grid of the same generator, and a batched spectral sweep
-(4 wavelengths x 2 geometries: batched against one-by-one throughput, and
-the batched mixed solver against plain FP64 solves in solves/s).
+residual 1e-8 on the 512^3 workload itself (``solve_1e-8``: the
+mixed-precision solver to 1e-8, its error against the FP64 fixed point --
+the same context continued to 1e-10 -- and the plain FP64 iteration run for
+the same wall time), the same comparison on a 128 x 128 x 256 grid of the
+generator where plain FP64 does reach 1e-8 (``solve_1e-8_small``), and a
+batched spectral sweep (batched against one-by-one throughput, and the
+batched mixed solver against plain FP64 in solves/s).
 
 The roofline entry also carries the bandwidth of a plain 4 GiB device copy
 measured in the same process (``copy_gbs``) and the sweep's fractions of it,
@@ -273,13 +276,14 @@ def adjoint_context(torch, thiim, pb, n_cells, w):
 def solve_context(torch, thiim, inputs, shape, tol=1e-8):
     """solves/s to relative residual tol: the plain FP64 iteration (blocked
     sweep, residual every 500 iterations) against the mixed-precision solver
-    (complex64 inner sweeps, T = 3, adaptive inner count), same inputs."""
+    (complex64 inner sweeps, two per pass, adaptive inner count), same
+    inputs."""
     nz, ny, nx = shape
     pb = inputs.solar_cell(nx, ny, nz, seed=10, npml=6, loss_range=(0.1, 0.5))
     out = {"grid": f"{nx}x{ny}x{nz}", "tol": tol,
            "workload": "solar_cell seed 10, loss in [0.1, 0.5], lambda 600 nm"}
     fields = {}
-    for name, kw, every in (("fp64", {}, 500), ("mixed", {"precision": "mixed", "t_block": 3}, 0)):
+    for name, kw, every in (("fp64", {}, 500), ("mixed", {"precision": "mixed"}, 0)):
         s = thiim.Solver(pb, storage="compact", **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -298,6 +302,73 @@ def solve_context(torch, thiim, inputs, shape, tol=1e-8):
     out["mixed_vs_fp64_physical_rel_diff"] = float(torch.linalg.vector_norm(a - b) /
                                                    torch.linalg.vector_norm(a))
     out["speedup_solves_per_s"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
+def solve_512_context(torch, thiim, dev, n, tol=1e-8, ref_tol=1e-10, m=2000):
+    """Time to solution on the benchmark workload itself (the n^3 problem):
+    the mixed-precision solver (complex64 inner sweeps, two per pass, m inner
+    sweeps per correction) to tol; the same context continued to ref_tol, whose
+    iterate is the FP64 fixed point to ref_tol (its residual is the FP64
+    one), gives the error of the tol solution; then the plain FP64 iteration
+    (temporally blocked sweep, residual every 500 iterations) for the same
+    wall time as the mixed solve took, reporting the residual it reached (or
+    its time, had it reached tol).  Progress is printed per slice."""
+    out = {"grid": f"{n}x{n}x{n}", "tol": tol,
+           "workload": "the benchmark problem (seed 3, 200 spheres, lambda 600 nm)",
+           "fixed_point_reference": f"the same mixed context continued to {ref_tol:g} "
+                                    "(FP64 residual)"}
+    s = thiim.Solver(dev, storage="compact", precision="mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps, r, t_tol, snap = 0, 1.0, None, None
+    for goal in (tol, ref_tol):
+        while r > goal and sweeps < 1000000:
+            rc, it, r = s.solve(goal, 3 * (m + 1), m)
+            sweeps += it
+            log(f"[bench] 512 mixed: {sweeps} sweeps, residual {r:.3e}, "
+                f"{time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        if snap is None:
+            t_tol = time.perf_counter() - t0
+            out["mixed"] = {"sweeps": sweeps, "rel_residual": r, "seconds": t_tol,
+                            "solves_per_s": 1.0 / t_tol}
+            x = s.fields()
+            snap = x[0::2] + x[1::2]
+            del x
+        else:
+            x = s.fields()
+            p = x[0::2] + x[1::2]
+            del x
+            out["mixed_to_ref"] = {"sweeps": sweeps, "rel_residual": r,
+                                   "seconds": time.perf_counter() - t0}
+            out["mixed_error_vs_fixed_point"] = float(torch.linalg.vector_norm(snap - p) /
+                                                      torch.linalg.vector_norm(p))
+            del p
+    del snap
+    s.close()
+    torch.cuda.empty_cache()
+    s = thiim.Solver(dev, storage="compact")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, r = 0, 1.0
+    while r > tol and time.perf_counter() - t0 < t_tol:
+        rc, it, r = s.solve(tol, 2000, 500)
+        its += it
+        log(f"[bench] 512 fp64: {its} iterations, residual {r:.3e}, "
+            f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    torch.cuda.empty_cache()
+    reached = r <= tol
+    out["fp64"] = {"iterations": its, "rel_residual": r, "seconds": dt, "reached_tol": reached,
+                   "solves_per_s": 1.0 / dt if reached else None,
+                   "solves_per_s_upper_bound": None if reached else 1.0 / dt}
+    # mixed solves/s over plain FP64's (a lower bound when FP64 did not get
+    # there in the same time)
+    out["speedup_solves_per_s"] = dt / t_tol
+    out["speedup_is_lower_bound"] = not reached
     return out
 
 
@@ -340,7 +411,7 @@ def spectral_context(torch, thiim, inputs, tol=1e-8):
         f"{out['one_by_one_fp64_glups']:.2f} GLUP/s")
     torch.cuda.empty_cache()
     t = time.perf_counter()
-    bt = thiim.Batch(probs, precision="mixed", t_block=3)
+    bt = thiim.Batch(probs, precision="mixed")
     rc, its, res = bt.solve(tol, 2000000, 0)
     bt.synchronize()
     dt_mixed = time.perf_counter() - t
@@ -479,10 +550,11 @@ def main():
         kernels["adjoint/compact"] = adjoint_context(torch, thiim, dev, N, w)
         del w
         torch.cuda.empty_cache()
-    solve = None
+    solve = solve_small = None
     if not args.no_solve:
+        solve = solve_512_context(torch, thiim, dev, n)
         nx_, ny_, nz_ = (int(v) for v in args.solve_grid.split("x"))
-        solve = solve_context(torch, thiim, inputs, (nz_, ny_, nx_))
+        solve_small = solve_context(torch, thiim, inputs, (nz_, ny_, nx_))
     spectral = None
     if not args.no_spectral:
         spectral = spectral_context(torch, thiim, inputs)
@@ -524,6 +596,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "solve_1e-8": solve,
+        "solve_1e-8_small": solve_small,
         "spectral_batch": spectral,
     }
     print(json.dumps(out), flush=True)

@@ -92,8 +92,9 @@ typedef struct {
     int t_block;      /* iterations per pass for THIIM_KERNEL_BLOCKED: 0 (auto,
                        * = 2), 1 or 2; a remainder runs through the fused sweep.
                        * With THIIM_PRECISION_MIXED, 3 is also allowed; the
-                       * complex64 inner sweeps run 3 iterations per pass for
-                       * 0 (auto) and 3, and 2 for 1 and 2 */
+                       * complex64 inner sweeps run 2 iterations per pass on
+                       * 32 x 32 regions for 0 (auto), 1 and 2, and 3 on
+                       * 32 x 16 regions for 3 */
     int tile_x, tile_y; /* fused sweep: tile 64x8, 32x8, 64x4 or 16x16; blocked
                          * sweep: region 64x8, 64x6 or 32x16 (columns x rows) of
                          * which the centre (x-2T) x (y-2T) is stored; 0x0 = auto */
@@ -157,7 +158,9 @@ int thiim_residual(thiim_ctx *ctx, double *rel_res);
  * 0.3).  The correction added to x is the mean of d over the last
  * Kp = round(2 pi / (omega tau T)) passes of T sweeps -- one period of the
  * modes that an iteration only rotates by e^{-i omega tau}, which the
- * complex64 rounding would otherwise leave in x for ever.  A split pair whose
+ * complex64 rounding would otherwise leave in x for ever; those passes sum
+ * d into a complex64 buffer as they store it, and x += sum / Kp follows in
+ * FP64 once per correction.  A split pair whose
  * two parts have identical coefficients on a plane (the z pairs everywhere,
  * the x and y pairs off the PML) enters a correction through its sum only,
  * half to each part: a MIXED solve determines the physical fields P x, not

@@ -49,6 +49,7 @@ struct Layout {
     size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
     size_t off_a, off_b;
     size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
+    size_t off_acc32;         // mixed precision: 12 complex64 arrays (window sum)
     size_t off_ce, off_p32;   // mixed precision: per-cell float4 records, nz plane rows
     size_t off_lam, off_g;    // adjoint: 4 x 12 + 3 complex128 arrays
     size_t total;
@@ -71,12 +72,14 @@ Layout layout_of(const thiim_grid* g) {
     off += (size_t)12 * L.S * 16;
     L.off_b = off;
     off += (size_t)12 * L.S * 16;
-    L.off_r32 = L.off_d32 = L.off_ce = L.off_p32 = 0;
+    L.off_r32 = L.off_d32 = L.off_acc32 = L.off_ce = L.off_p32 = 0;
     if (g->precision == THIIM_PRECISION_MIXED) {
         L.off_r32 = off;
         off += (size_t)12 * L.S * 8;
         L.off_d32 = off;
         off += (size_t)24 * L.S * 8;
+        L.off_acc32 = off;
+        off += (size_t)12 * L.S * 8;
         L.off_ce = off;
         off += (size_t)L.S * 16;
         L.off_p32 = off;
@@ -163,6 +166,7 @@ struct thiim_ctx {
     int t_block, region_x, region_y, bz_chunk;  // blocked sweep
     float2* r32;                                // mixed precision buffers
     float2* d32[2];
+    float2* acc32;                // window sum of the inner passes
     float4* ce32;                 // per-cell complex64 E-coefficient records
     thiim::PlaneCoef32* p32;      // per-plane complex64 H coefficients
     int inner_t, inner_rx, inner_ry, inner_chunk;
@@ -239,13 +243,15 @@ int resolve_tiles(thiim_ctx* c) {
     const int ox = c->region_x - 2 * c->t_block, oy = c->region_y - 2 * c->t_block;
     const long long btiles = (long long)((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy);
     c->bz_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, btiles, c->ncu);
-    // complex64 inner sweeps of the mixed solver: region 32 x 16, T = 3 unless
-    // 1 or 2 is asked for (T = 3: 101 B per lattice update against 152)
-    c->inner_t = g.t_block == 1 || g.t_block == 2 ? 2 : 3;
+    // complex64 inner sweeps of the mixed solver: two per pass on 32 x 32
+    // regions (four waves per SIMD), or three per pass on 32 x 16 regions
+    // when t_block = 3 is asked for (two waves per SIMD; 12% slower per sweep
+    // at 512^3)
+    c->inner_t = g.t_block == 3 ? 3 : 2;
     c->inner_rx = 32;
-    c->inner_ry = 16;
-    const long long itiles = (long long)((g.nx + 32 - 2 * c->inner_t - 1) / (32 - 2 * c->inner_t)) *
-                             ((g.ny + 16 - 2 * c->inner_t - 1) / (16 - 2 * c->inner_t));
+    c->inner_ry = c->inner_t == 2 ? 32 : 16;
+    const int iox = c->inner_rx - 2 * c->inner_t, ioy = c->inner_ry - 2 * c->inner_t;
+    const long long itiles = (long long)((g.nx + iox - 1) / iox) * ((g.ny + ioy - 1) / ioy);
     c->inner_chunk = g.z_chunk > 0 ? g.z_chunk : auto_chunk(g, itiles, c->ncu);
     return THIIM_OK;
 }
@@ -336,6 +342,7 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->r32 = L.off_r32 ? (float2*)(c->ws + L.off_r32) : nullptr;
     c->d32[0] = L.off_d32 ? (float2*)(c->ws + L.off_d32) : nullptr;
     c->d32[1] = L.off_d32 ? c->d32[0] + 12 * L.S : nullptr;
+    c->acc32 = L.off_acc32 ? (float2*)(c->ws + L.off_acc32) : nullptr;
     c->ce32 = L.off_ce ? (float4*)(c->ws + L.off_ce) : nullptr;
     c->p32 = L.off_p32 ? (thiim::PlaneCoef32*)(c->ws + L.off_p32) : nullptr;
     c->lam[0] = L.off_lam ? (double2*)(c->ws + L.off_lam) : nullptr;
@@ -480,8 +487,9 @@ namespace {
 // period 2 pi / (w tau) of those modes: the average of l^k over a period is
 // ~0, so the averaged d carries r / (1 - l) for them (to a factor 1/(2 Kp))
 // while every other mode mu keeps |weight| <= 1 (the average of mu^k), i.e.
-// nothing is amplified.  x accumulates the window in FP64 (x += d / Kp after
-// each of those passes).
+// nothing is amplified.  The inner passes of the window sum their d into a
+// complex64 buffer as they store it, and x += sum / Kp follows in FP64 once
+// per correction.
 //
 // check_every > 0 fixes the inner sweeps per correction; 0 adapts it: start
 // at max(64, 2 Kp T) and double (up to kMaxInner) while a correction gains
@@ -533,15 +541,17 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
         e = thiim::launch_copy32(c->r32, c->d32[0], c->L.S, c->L.N, c->stream);
         int di = 0;
         for (int p = 0; e == hipSuccess && p < passes; ++p) {
+            // the last Kp passes also sum what they store into acc32
+            const int acc_mode = p < passes - Kp ? 0 : (p == passes - Kp ? 1 : 2);
             e = thiim::launch_inner32(c->cv, c->ce32, c->p32, c->r32, c->d32[di],
-                                      c->d32[1 - di], c->geo, T, c->inner_rx, c->inner_ry,
-                                      c->inner_chunk, c->stream);
+                                      c->d32[1 - di], c->acc32, acc_mode, c->geo, T,
+                                      c->inner_rx, c->inner_ry, c->inner_chunk, c->stream);
             di = 1 - di;
-            if (e == hipSuccess && p >= passes - Kp)
-                e = thiim::launch_accum(c->F[c->cur], c->d32[di], 1.0 / Kp, c->cv.P,
-                                        (long long)c->g.nx * c->g.ny, c->L.S, c->L.N,
-                                        c->stream);
         }
+        // x += (window sum) / Kp in FP64
+        if (e == hipSuccess)
+            e = thiim::launch_accum(c->F[c->cur], c->acc32, 1.0 / Kp, c->cv.P,
+                                    (long long)c->g.nx * c->g.ny, c->L.S, c->L.N, c->stream);
         if (e != hipSuccess) return hip_fail(e, "mixed: inner sweeps");
         done += passes * T;           // sweeps run (d = r is a copy)
         c->iters += 1 + passes * T;   // equivalent plain iterations
@@ -1225,6 +1235,8 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                         it.ph2c = make_float2((float)c->cv.K.ph2c.x, (float)c->cv.K.ph2c.y);
                         it.A = c->d32[par];
                         it.B = c->d32[1 - par];
+                        it.acc = c->acc32;
+                        it.window = Kp[i];
                         it.g = c->geo;
                         it.kchunk = c->inner_chunk;
                         const int ox = c->inner_rx - 2 * gr.T, oy = c->inner_ry - 2 * gr.T;
@@ -1257,17 +1269,19 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                     if (err == hipSuccess)
                         err = thiim::launch_copy32(b->ctx[i]->r32, b->ctx[i]->d32[0],
                                                    b->ctx[i]->L.S, b->ctx[i]->L.N, b->stream);
-                for (int p = 0; err == hipSuccess && p < P; ++p) {
+                // each item sums its last Kp passes into its acc32
+                int wmax = 0;
+                for (int i : gr.members) wmax = std::max(wmax, Kp[i]);
+                for (int p = 0; err == hipSuccess && p < P; ++p)
                     err = thiim::launch_inner32_batch(gr.dev[p & 1], (int)gr.members.size(),
-                                                      gr.total, gr.T, 32, 16, b->queue, b->ncu,
-                                                      b->stream);
-                    for (int i : gr.members) {
-                        if (err != hipSuccess || p < P - Kp[i]) continue;
-                        thiim_ctx* c = b->ctx[i];
-                        err = thiim::launch_accum(c->F[c->cur], c->d32[(p + 1) & 1], 1.0 / Kp[i],
-                                                  c->cv.P, (long long)c->g.nx * c->g.ny,
-                                                  c->L.S, c->L.N, b->stream);
-                    }
+                                                      gr.total, gr.T, P - 1 - p, wmax, b->queue,
+                                                      b->ncu, b->stream);
+                for (int i : gr.members) {
+                    if (err != hipSuccess) break;
+                    thiim_ctx* c = b->ctx[i];
+                    err = thiim::launch_accum(c->F[c->cur], c->acc32, 1.0 / Kp[i], c->cv.P,
+                                              (long long)c->g.nx * c->g.ny, c->L.S, c->L.N,
+                                              b->stream);
                 }
             }
             return err;

@@ -76,6 +76,8 @@ struct BatchItem32 {
     float2 ph, phc, ph2, ph2c;
     const float2* A;
     float2* B;
+    float2* acc;  // window sum of the correction (pair-sum form)
+    int window;   // passes in the window: the last `window` passes of a step
     Geo g;
     int kchunk;
     int tile_begin;
@@ -109,9 +111,13 @@ hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, cons
 // per-plane H table (once per context), then inner sweeps d <- M d + r.
 hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef32* P32,
                          hipStream_t s);
+// One complex64 inner pass d <- M d + r (T sweeps: T = 2 on 32 x 32 regions,
+// T = 3 on 32 x 16), adding the stored d to acc with acc_mode 1 (acc = d) or
+// 2 (acc += d).
 hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                          const float2* r, const float2* A, float2* B, const Geo& g, int T,
-                          int rx, int ry, int kchunk, hipStream_t s);
+                          const float2* r, const float2* A, float2* B, float2* acc,
+                          int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
+                          hipStream_t s);
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
                          long long S, long long N, long long nxy, double* part, int nblk,
                          double* out, hipStream_t s);
@@ -130,8 +136,10 @@ hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int
                               int tile_y, unsigned int* queue, int ncu, hipStream_t s);
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
                                 int ry, unsigned int* queue, int ncu, hipStream_t s);
-hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
-                                int ry, unsigned int* queue, int ncu, hipStream_t s);
+// left: passes of the step after this one (an item sums its last `window`);
+// max_window: the largest window of the items
+hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int left,
+                                int max_window, unsigned int* queue, int ncu, hipStream_t s);
 // ||P(B - A)||^2 and ||P B||^2 over the physical components c0..5 (0: all
 // six, 3: E only) into out[0], out[1].
 hipError_t launch_resid(const double2* A, const double2* B, long long S, long long N,
@@ -163,6 +171,8 @@ hipError_t launch_adj_source(const double2* X, const double2* eps, const double*
 hipError_t launch_adj_grad(const CoefView& cv, const double2* X, const double2* Y,
                            const double2* L, const double* w, const Geo& g, double2* grad,
                            hipStream_t s);
+hipError_t launch_stream_probe(const double2* in, double2* out, long long S, long long n,
+                               int nin, int nout, int ncu, hipStream_t s);
 hipError_t launch_fill_zero(double2* p, long long n, hipStream_t s);
 hipError_t launch_copy(const double2* src, double2* dst, long long n, hipStream_t s);
 

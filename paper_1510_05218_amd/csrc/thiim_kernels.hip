@@ -409,6 +409,8 @@ __host__ __device__ __forceinline__ CompactCoefs compact_view(const CoefView& v)
 template <class CP>
 struct Pol64 {
     using V = double2;
+    static constexpr int MIN_WAVES = 0;  // no occupancy request
+    static constexpr bool XL = false;    // neighbour sums through LDS
     static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
     static constexpr bool H_SRC_AFTER = false;
     static constexpr bool CARRY = false;
@@ -481,6 +483,8 @@ __host__ __device__ __forceinline__ float2 to32(double2 v) {
 struct Pol32 {
     using V = float2;
     using CRec = float4;
+    static constexpr int MIN_WAVES = 0;
+    static constexpr bool XL = false;
     static constexpr int HMASK = 0, EMASK = SRC_MASK_ALL;
     static constexpr bool H_SRC_AFTER = true;
     // sources and the E-coefficient record are loaded once, by the first
@@ -493,6 +497,11 @@ struct Pol32 {
     const float2* __restrict__ r;        // 12 arrays, stride S
     long long S;
     float2 ph, phc, ph2, ph2c;
+    // Window sum of the mixed solver's correction: the pass also adds what it
+    // stores to acc (12 arrays in the same pair-sum form): acc_mode 0 none,
+    // 1 acc = d (first pass of the window), 2 acc += d.
+    float2* __restrict__ acc;
+    int acc_mode;
     // Pair-sum form.  Where both parts of a split pair have identical
     // coefficients (PlaneCoef32::hsym / esym for the x and y pairs, always for
     // the z pairs) one pass maps the pair's sum to t * sum + (both parts'
@@ -512,18 +521,33 @@ struct Pol32 {
             v[3] = ldo(F + 3 * S + po, bo);
         }
     }
-    __device__ __forceinline__ void store_pairs(V* __restrict__ F, bool sym, long long po,
-                                                uint32_t bo, const V v[6]) const {
-        if (sym) {
-            sto(F + 0 * S + po, bo, cadd(v[0], v[1]));
-            sto(F + 2 * S + po, bo, cadd(v[2], v[3]));
-        } else {
-            sto(F + 0 * S + po, bo, v[0]);
-            sto(F + 1 * S + po, bo, v[1]);
-            sto(F + 2 * S + po, bo, v[2]);
-            sto(F + 3 * S + po, bo, v[3]);
+    // one stored value of part q: to F and, for ACC policies, by acc_mode
+    // into Acc
+    template <bool ACC>
+    __device__ __forceinline__ void put(V* __restrict__ F, V* __restrict__ Acc, int q,
+                                        long long po, uint32_t bo, V w) const {
+        sto(F + q * S + po, bo, w);
+        if constexpr (ACC) {
+            if (acc_mode) {
+                if (acc_mode == 2) w = cadd(ldo(Acc + q * S + po, bo), w);
+                sto(Acc + q * S + po, bo, w);
+            }
         }
-        sto(F + 4 * S + po, bo, cadd(v[4], v[5]));
+    }
+    // the six parts in pair-sum form
+    template <bool ACC>
+    __device__ __forceinline__ void store_pairs(V* __restrict__ F, V* __restrict__ Acc, bool sym,
+                                                long long po, uint32_t bo, const V v[6]) const {
+        if (sym) {
+            put<ACC>(F, Acc, 0, po, bo, cadd(v[0], v[1]));
+            put<ACC>(F, Acc, 2, po, bo, cadd(v[2], v[3]));
+        } else {
+            put<ACC>(F, Acc, 0, po, bo, v[0]);
+            put<ACC>(F, Acc, 1, po, bo, v[1]);
+            put<ACC>(F, Acc, 2, po, bo, v[2]);
+            put<ACC>(F, Acc, 3, po, bo, v[3]);
+        }
+        put<ACC>(F, Acc, 4, po, bo, cadd(v[4], v[5]));
     }
     __device__ __forceinline__ void load_h_src(int k, long long po, uint32_t bo,
                                                V src[6]) const {
@@ -543,11 +567,11 @@ struct Pol32 {
     }
     __device__ __forceinline__ void store_h(V* F, long long, int k, long long po, uint32_t bo,
                                             const V v[6]) const {
-        store_pairs(F, P32[k].hsym != 0, po, bo, v);
+        store_pairs<false>(F, acc, P32[k].hsym != 0, po, bo, v);
     }
     __device__ __forceinline__ void store_e(V* F, long long, int k, long long po, uint32_t bo,
                                             const V v[6]) const {
-        store_pairs(F, P32[k].esym != 0, po, bo, v);
+        store_pairs<false>(F, acc + 6 * S, P32[k].esym != 0, po, bo, v);
     }
     __device__ __forceinline__ CRec load_crec(long long po, uint32_t bo) const {
         return ldo(ce + po, bo);
@@ -578,6 +602,51 @@ struct Pol32 {
         t[5] = t0; c[5] = c0;
     }
 };
+
+// Pol32 with the sources and the coefficient record read by every stage at
+// its own plane (the later reads mostly from L2) instead of handed down the
+// stage pipeline in registers, and the neighbour sums exchanged across lanes:
+// with two iterations per pass a column needs at most 128 VGPRs, so 32 x 32
+// regions (1024 threads) run at four waves per SIMD.  Measured at 512^3:
+// 6.9 ms per two-sweep pass against 12.1-12.5 ms per three-sweep pass of
+// Pol32 on 32 x 16 regions (two waves per SIMD); three sweeps per pass on 32 x
+// 24 regions or the same kernel on 32 x 16 regions at two workgroups per CU
+// measured slower.
+struct Pol32R : Pol32 {
+    static constexpr bool CARRY = false;
+    static constexpr bool CARRY_REC = false;
+    static constexpr int MIN_WAVES = 4;
+    static constexpr bool XL = true;
+    __device__ __forceinline__ void hcoef(int k, long long po, uint32_t bo, V t[6], V c[6],
+                                          V src[6]) const {
+        hcoef_c(k, t, c);
+        load_h_src(k, po, bo, src);
+    }
+    __device__ __forceinline__ void ecoef(int k, long long po, uint32_t bo, V t[6], V c[6],
+                                          V src[6]) const {
+        ecoef_c(k, load_crec(po, bo), t, c);
+        load_e_src(k, po, bo, src);
+    }
+};
+
+// The same passes that also sum what they store into the window sum acc (the
+// last Kp passes of a correction): separate kernels, so that the other
+// passes carry no code or registers for it.
+template <class Base>
+struct WithAcc : Base {
+    using V = typename Base::V;
+    __device__ __forceinline__ void store_h(V* F, long long, int k, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        this->template store_pairs<true>(F, this->acc, this->P32[k].hsym != 0, po, bo, v);
+    }
+    __device__ __forceinline__ void store_e(V* F, long long, int k, long long po, uint32_t bo,
+                                            const V v[6]) const {
+        this->template store_pairs<true>(F, this->acc + 6 * this->S, this->P32[k].esym != 0, po,
+                                         bo, v);
+    }
+};
+using Pol32A = WithAcc<Pol32>;
+using Pol32RA = WithAcc<Pol32R>;
 
 // Coefficient data of the complex64 inner sweeps, built once per context.
 // Per cell: {+-r0, r1, b0, b1} with r_i = 1/d_i the real factor of t and c in
@@ -954,36 +1023,136 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Cross-lane moves of the temporally blocked passes.  A wavefront holds 64
+// consecutive columns of a region row (RX = 64) or two rows of 32 (RX = 32,
+// lanes 0-31 the lower row, 32-63 the upper).  The x neighbours of every lane
+// are its wave neighbours (DPP wave shifts, no LDS); with two rows per wave
+// the y neighbour of half of the rows is in the same wave (a swap of the two
+// 32-lane halves).  Lanes at a row end receive another row's value or zero:
+// they are ring columns whose results never reach a stored cell.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ unsigned int dpp_u(unsigned int v) {
+    return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kWaveShr1 = 0x138;  // lane L reads lane L - 1
+constexpr int kWaveShl1 = 0x130;  // lane L reads lane L + 1
+typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
+
+template <int CTRL>
+__device__ __forceinline__ double2 dpp_move(double2 v) {
+    const u32x4 w = __builtin_bit_cast(u32x4, v);
+    u32x4 r;
+    r.x = dpp_u<CTRL>(w.x);
+    r.y = dpp_u<CTRL>(w.y);
+    r.z = dpp_u<CTRL>(w.z);
+    r.w = dpp_u<CTRL>(w.w);
+    return __builtin_bit_cast(double2, r);
+}
+template <int CTRL>
+__device__ __forceinline__ float2 dpp_move(float2 v) {
+    const u32x2v w = __builtin_bit_cast(u32x2v, v);
+    u32x2v r;
+    r.x = dpp_u<CTRL>(w.x);
+    r.y = dpp_u<CTRL>(w.y);
+    return __builtin_bit_cast(float2, r);
+}
+// value of lane L - 1 / L + 1
+template <class V>
+__device__ __forceinline__ V from_xm(V v) { return dpp_move<kWaveShr1>(v); }
+template <class V>
+__device__ __forceinline__ V from_xp(V v) { return dpp_move<kWaveShl1>(v); }
+
+// Swap of the 32-lane halves: lanes 32-63 receive lanes 0-31 (the row below),
+// lanes 0-31 receive lanes 32-63 (the row above).
+__device__ __forceinline__ unsigned int half_swap_u(unsigned int v, bool upper) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return upper ? r[0] : r[1];
+}
+__device__ __forceinline__ double2 half_swap(double2 v, bool upper) {
+    const u32x4 w = __builtin_bit_cast(u32x4, v);
+    u32x4 r;
+    r.x = half_swap_u(w.x, upper);
+    r.y = half_swap_u(w.y, upper);
+    r.z = half_swap_u(w.z, upper);
+    r.w = half_swap_u(w.w, upper);
+    return __builtin_bit_cast(double2, r);
+}
+__device__ __forceinline__ float2 half_swap(float2 v, bool upper) {
+    const u32x2v w = __builtin_bit_cast(u32x2v, v);
+    u32x2v r;
+    r.x = half_swap_u(w.x, upper);
+    r.y = half_swap_u(w.y, upper);
+    return __builtin_bit_cast(float2, r);
+}
+
+// ---------------------------------------------------------------------------
 // Temporally blocked pass: T THIIM iterations per HBM pass, A -> B.
 //
-// A workgroup covers a region of RX x RY columns (lanes along x) and streams
-// z.  Each thread keeps one column for the whole
-// stream and for all T stages (fixed execution to data): the stage outputs it
-// needs one plane later -- old values and z-neighbour sums -- stay in its
-// registers, and the x/y-neighbour sums of every stage pass through LDS.
+// A workgroup covers a region of RX x RY columns (lanes along x, RX = 32 or
+// 64) and streams z.  Each thread keeps one column for the whole stream and
+// for all T stages (fixed execution to data): the stage outputs it needs one
+// plane later -- old values and z-neighbour sums -- stay in its registers.
 // At step k stage s updates H_s at plane k-s+1 and E_s at plane k-s, so one
 // HBM read of plane k feeds all T stages (GPU form of the wavefront in z).
+// Neighbour sums: x neighbours and the y neighbours inside a wavefront by
+// cross-lane moves; only the rows whose y neighbour is in another wavefront
+// exchange through LDS (the upper row of each wave its E sums E_x, E_z for
+// the y-1 reads of the next wave, the lower row its H sums H_x, H_z for the
+// y+1 reads of the previous one; H by step parity, read one step later):
+// 3 values per exchanged column and stage.
 // Only the centre (RX-2T) x (RY-2T) columns are valid after T stages; they
 // are stored, the ring is recomputed by the neighbouring workgroups.  Region
-// cells beyond the ring read clamped neighbours: their (unused) results
-// never reach a stored cell.  z chunks overlap by T-1 planes.
-// Each stage reads its own coefficients: with the 40-array layout that is
-// 448 B per column per stage, with the compact storage 16 B (eps).
+// cells at the ring's outer edge read neighbours of another row or zero:
+// their (unused) results never reach a stored cell.  z chunks overlap by T-1
+// planes.  Each stage reads its own coefficients: with the 40-array layout
+// that is 448 B per column per stage, with the compact storage 16 B (eps).
 // ---------------------------------------------------------------------------
-template <int RX, int RY, int T, class P>
+template <int RX, int RY, int T, bool XL, class P>
 __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* __restrict__ A,
                                              typename P::V* __restrict__ B, const Geo& g,
                                              int kchunk, const Tile TT) {
     using V = typename P::V;
     constexpr int R = RX * RY;
+    static_assert(!XL || RX == 32 || RX == 64, "cross-lane regions are 32 or 64 columns wide");
+    constexpr bool TWO_ROWS = XL && RX == 32;     // two region rows per wavefront
+    constexpr int LR = TWO_ROWS ? RY / 2 : RY;    // rows exchanged through LDS
+    static_assert(!TWO_ROWS || RY % 2 == 0, "RX = 32 needs an even row count");
     constexpr int OX = RX - 2 * T, OY = RY - 2 * T;  // stored tile
     static_assert(OY >= 1, "region too small for T stages");
-    __shared__ V LE[T][3][R];     // E_{s} sums, s = 0..T-1 (current plane)
-    __shared__ V LH[T][2][3][R];  // H_{s+1} sums, by step parity
+    // LDS: cross-lane form: E_x, E_z sums of the exchanged rows per stage and
+    // H_x, H_z by step parity; LDS form: all three sums of every column
+    constexpr int NE = XL ? T * 2 * LR * RX : T * 3 * R;
+    constexpr int NH = XL ? T * 2 * 2 * LR * RX : T * 2 * 3 * R;
+    __shared__ V lds[NE + NH];
+    V* const LE = lds;
+    V* const LH = lds + NE;
 
     const long long S = g.S;
     const long long plane = (long long)g.nx * g.ny;
     const int lane = threadIdx.x % RX, row = threadIdx.x / RX;
+    const bool upper = TWO_ROWS && (threadIdx.x & 32);
+    const int xrow = TWO_ROWS ? (int)(threadIdx.x / 64) : row;  // LDS row index
+    // cross-lane form: which rows write / read LDS (with two rows per wave the
+    // upper row writes E and reads H, the lower row writes H and reads E)
+    const bool e_w = !TWO_ROWS || upper, e_r = !TWO_ROWS || !upper;
+    const bool h_w = !TWO_ROWS || !upper, h_r = !TWO_ROWS || upper;
+    const int e_src = xrow > 0 ? xrow - 1 : 0;          // slot of the row below
+    const int h_src = xrow < LR - 1 ? xrow + 1 : xrow;  // slot of the row above
+    // LDS form: own slot and clamped x/y neighbour slots
+    const int me = row * RX + lane;
+    const int xm = row * RX + (lane > 0 ? lane - 1 : 0);
+    const int xp = row * RX + (lane < RX - 1 ? lane + 1 : RX - 1);
+    const int ym = (row > 0 ? row - 1 : 0) * RX + lane;
+    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * RX + lane;
+    // slot of E sum c of stage s / H sum c of stage s, parity p
+    auto le = [&](int s_, int c, int idx) -> V& {
+        return XL ? LE[((s_ * 2 + c) * LR + idx) * RX + lane] : LE[(s_ * 3 + c) * R + idx];
+    };
+    auto lh = [&](int s_, int p_, int c, int idx) -> V& {
+        return XL ? LH[(((s_ * 2 + p_) * 2 + c) * LR + idx) * RX + lane]
+                  : LH[((s_ * 2 + p_) * 3 + c) * R + idx];
+    };
     const int ux = TT.bx * OX - T + lane;  // unwrapped global column
     const int uy = TT.by * OY - T + row;
     int gi = ux, gj = uy;
@@ -991,22 +1160,13 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
     const bool own = lane >= T && lane < RX - T && row >= T && row < RY - T &&
                      ux < g.nx && uy < g.ny;
     const uint32_t bo = valid ? 16u * (uint32_t)(gj * g.nx + gi) : 0u;
-    const int me = row * RX + lane;
-    const int xm = row * RX + (lane > 0 ? lane - 1 : 0);
-    const int xp = row * RX + (lane < RX - 1 ? lane + 1 : RX - 1);
-    const int ym = (row > 0 ? row - 1 : 0) * RX + lane;
-    const int yp = (row < RY - 1 ? row + 1 : RY - 1) * RX + lane;
 
     const int k0 = TT.bz * kchunk;
     const int k1 = min(g.nz, k0 + kchunk);
     const int ks = max(0, k0 - (T - 1));
     const int kend = min(k1 + T - 1, g.nz + T - 1);
 
-    for (int i = threadIdx.x; i < T * 3 * R; i += RX * RY) {
-        (&LE[0][0][0])[i] = vzero<V>();
-        (&LH[0][0][0][0])[i] = vzero<V>();
-        (&LH[0][0][0][0])[i + T * 3 * R] = vzero<V>();
-    }
+    for (int i = threadIdx.x; i < NE + NH; i += R) lds[i] = vzero<V>();
 
     const V* AE = A + 6 * S;
     V* BE = B + 6 * S;
@@ -1065,17 +1225,45 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
         if constexpr (P::CARRY_REC) {
             if (valid && k >= 1 && k - 1 < g.nz) crq[0] = pol.load_crec((k - 1) * plane, bo);
         }
-        // ---- E_0(k) sums into LDS
-        LE[0][0][me] = cadd(e0c[0], e0c[1]);
-        LE[0][1][me] = cadd(e0c[2], e0c[3]);
-        LE[0][2][me] = cadd(e0c[4], e0c[5]);
+        // ---- E_0(k) sums: the cross-wave rows through LDS
+        V esum[3] = {cadd(e0c[0], e0c[1]), cadd(e0c[2], e0c[3]), cadd(e0c[4], e0c[5])};
+        if constexpr (XL) {
+            if (e_w) {
+                le(0, 0, xrow) = esum[0];
+                le(0, 1, xrow) = esum[2];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) le(0, c, me) = esum[c];
+        }
         __syncthreads();
 
         V hn[T][6], en[T][6], hns[T][3];
 #pragma unroll
         for (int s = 1; s <= T; ++s) {
-            // ---- H_s at plane kh
+            // ---- H_s at plane kh, from the sums esum of E_{s-1}(kh)
             const int kh = k - s + 1;
+            ENbrT<V> nb;
+            nb.ex = esum[0];
+            nb.ey = esum[1];
+            nb.ez = esum[2];
+            if constexpr (XL) {
+                nb.ey_xm = from_xm(esum[1]);
+                nb.ez_xm = from_xm(esum[2]);
+                if constexpr (TWO_ROWS) {
+                    nb.ex_ym = half_swap(esum[0], upper);
+                    nb.ez_ym = half_swap(esum[2], upper);
+                }
+                if (e_r) {
+                    nb.ex_ym = le(s - 1, 0, e_src);
+                    nb.ez_ym = le(s - 1, 1, e_src);
+                }
+            } else {
+                nb.ex_ym = le(s - 1, 0, ym);
+                nb.ez_ym = le(s - 1, 2, ym);
+                nb.ey_xm = le(s - 1, 1, xm);
+                nb.ez_xm = le(s - 1, 2, xm);
+            }
             V h[6], hsum[3] = {vzero<V>(), vzero<V>(), vzero<V>()};
 #pragma unroll
             for (int q = 0; q < 6; ++q) h[q] = vzero<V>();
@@ -1090,16 +1278,8 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                     for (int q = 0; q < 6; ++q) h[q] = hc[s - 1][q];
                 }
                 const V* zp = (s == 1) ? e0p : ep[s - 1];  // E_{s-1}(kh-1)
-                ENbrT<V> nb;
-                nb.ex = LE[s - 1][0][me];
-                nb.ey = LE[s - 1][1][me];
-                nb.ez = LE[s - 1][2][me];
                 nb.ex_zm = cadd(zp[0], zp[1]);
                 nb.ey_zm = cadd(zp[2], zp[3]);
-                nb.ex_ym = LE[s - 1][0][ym];
-                nb.ez_ym = LE[s - 1][2][ym];
-                nb.ey_xm = LE[s - 1][1][xm];
-                nb.ez_xm = LE[s - 1][2][xm];
                 V t[6], c[6], src[6];
                 if constexpr (P::CARRY) {
                     pol.hcoef_c(kh, t, c);
@@ -1119,16 +1299,57 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 if (s == T && own && kh >= k0 && kh < k1) pol.store_h(B, S, kh, po, bo, h);
             }
             const V hx = hsum[0], hy = hsum[1], hz = hsum[2];
-            LH[s - 1][par][0][me] = hx;
-            LH[s - 1][par][1][me] = hy;
-            LH[s - 1][par][2][me] = hz;
+            if constexpr (XL) {
+                if (h_w) {
+                    lh(s - 1, par, 0, xrow) = hx;
+                    lh(s - 1, par, 1, xrow) = hz;
+                }
+            } else {
+                lh(s - 1, par, 0, me) = hx;
+                lh(s - 1, par, 1, me) = hy;
+                lh(s - 1, par, 2, me) = hz;
+            }
             hns[s - 1][0] = hx;
             hns[s - 1][1] = hy;
             hns[s - 1][2] = hz;
 #pragma unroll
             for (int q = 0; q < 6; ++q) hn[s - 1][q] = h[q];
-            // ---- E_s at plane ke (old value E_{s-1}(ke))
+            // ---- E_s at plane ke (old value E_{s-1}(ke)), from the sums of
+            // H_s at ke (computed one step earlier) and at ke + 1 (just now)
             const int ke = k - s;
+            HNbrT<V> hb;
+            if (s == T) {
+                hb.hx = hTx;
+                hb.hy = hTy;
+                hb.hz = hTz;
+            } else if constexpr (P::H_SRC_AFTER) {
+                hb.hx = hcs[s][0];
+                hb.hy = hcs[s][1];
+                hb.hz = hcs[s][2];
+            } else {
+                hb.hx = cadd(hc[s][0], hc[s][1]);
+                hb.hy = cadd(hc[s][2], hc[s][3]);
+                hb.hz = cadd(hc[s][4], hc[s][5]);
+            }
+            hb.hx_zp = hx;
+            hb.hy_zp = hy;
+            if constexpr (XL) {
+                hb.hy_xp = from_xp(hb.hy);
+                hb.hz_xp = from_xp(hb.hz);
+                if constexpr (TWO_ROWS) {
+                    hb.hx_yp = half_swap(hb.hx, upper);
+                    hb.hz_yp = half_swap(hb.hz, upper);
+                }
+                if (h_r) {
+                    hb.hx_yp = lh(s - 1, par ^ 1, 0, h_src);
+                    hb.hz_yp = lh(s - 1, par ^ 1, 1, h_src);
+                }
+            } else {
+                hb.hx_yp = lh(s - 1, par ^ 1, 0, yp);
+                hb.hz_yp = lh(s - 1, par ^ 1, 2, yp);
+                hb.hy_xp = lh(s - 1, par ^ 1, 1, xp);
+                hb.hz_xp = lh(s - 1, par ^ 1, 2, xp);
+            }
             V e[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) e[q] = vzero<V>();
@@ -1136,26 +1357,6 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 const long long po = ke * plane;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) e[q] = (s == 1) ? e0p[q] : ep[s - 1][q];
-                HNbrT<V> nb;
-                if (s == T) {
-                    nb.hx = hTx;
-                    nb.hy = hTy;
-                    nb.hz = hTz;
-                } else if constexpr (P::H_SRC_AFTER) {
-                    nb.hx = hcs[s][0];
-                    nb.hy = hcs[s][1];
-                    nb.hz = hcs[s][2];
-                } else {
-                    nb.hx = cadd(hc[s][0], hc[s][1]);
-                    nb.hy = cadd(hc[s][2], hc[s][3]);
-                    nb.hz = cadd(hc[s][4], hc[s][5]);
-                }
-                nb.hx_zp = hx;
-                nb.hy_zp = hy;
-                nb.hx_yp = LH[s - 1][par ^ 1][0][yp];
-                nb.hz_yp = LH[s - 1][par ^ 1][2][yp];
-                nb.hy_xp = LH[s - 1][par ^ 1][1][xp];
-                nb.hz_xp = LH[s - 1][par ^ 1][2][xp];
                 V t[6], c[6], src[6];
                 if constexpr (P::CARRY) {
                     pol.ecoef_c(ke, crq[s - 1], t, c);
@@ -1166,15 +1367,25 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 } else {
                     pol.ecoef(ke, po, bo, t, c, src);
                 }
-                update_e_t<P::EMASK>(e, t, c, src, nb);
+                update_e_t<P::EMASK>(e, t, c, src, hb);
                 if (s == T && own && ke >= k0 && ke < k1) pol.store_e(BE, S, ke, po, bo, e);
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) en[s - 1][q] = e[q];
             if (s < T) {
-                LE[s][0][me] = cadd(e[0], e[1]);
-                LE[s][1][me] = cadd(e[2], e[3]);
-                LE[s][2][me] = cadd(e[4], e[5]);
+                // E_s(ke) = E_s(k - (s+1) + 1): the input of stage s + 1
+                esum[0] = cadd(e[0], e[1]);
+                esum[1] = cadd(e[2], e[3]);
+                esum[2] = cadd(e[4], e[5]);
+                if constexpr (XL) {
+                    if (e_w) {
+                        le(s, 0, xrow) = esum[0];
+                        le(s, 1, xrow) = esum[2];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) le(s, c, me) = esum[c];
+                }
                 __syncthreads();
             }
             if (s == T) {
@@ -1213,11 +1424,12 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
 }
 
 template <int RX, int RY, int T, class P>
-__global__ __launch_bounds__(RX* RY) void k_blocked(P pol, const typename P::V* __restrict__ A,
+__global__ __launch_bounds__(RX* RY, (P::MIN_WAVES > 0 ? P::MIN_WAVES : 1)) void k_blocked(
+    P pol, const typename P::V* __restrict__ A,
                                                     typename P::V* __restrict__ B, Geo g,
                                                     int kchunk) {
     constexpr int OX = RX - 2 * T, OY = RY - 2 * T;
-    blocked_body<RX, RY, T>(pol, A, B, g, kchunk,
+    blocked_body<RX, RY, T, P::XL>(pol, A, B, g, kchunk,
                             tile_of<kBlockedStrip>((g.nx + OX - 1) / OX, (g.ny + OY - 1) / OY,
                                                    (g.nz + kchunk - 1) / kchunk));
 }
@@ -1294,13 +1506,15 @@ __global__ __launch_bounds__(TX* TY) void k_fused_batch(const BatchItem* __restr
     });
 }
 
-template <int RX, int RY, int T>
-__global__ __launch_bounds__(RX* RY) void k_inner32_batch(const BatchItem32* __restrict__ items,
-                                                          int nitems, int total,
-                                                          unsigned int* __restrict__ queue) {
+template <int RX, int RY, int T, class P>
+__global__ __launch_bounds__(RX* RY, (P::MIN_WAVES > 0 ? P::MIN_WAVES : 1)) void k_inner32_batch(
+    const BatchItem32* __restrict__ items, int nitems, int total, int left,
+    unsigned int* __restrict__ queue) {
     run_queue(queue, total, [&](int t) {
         const BatchItem32& it = items[batch_find(items, nitems, t)];
-        Pol32 pol;
+        P pol;
+        pol.acc = it.acc;
+        pol.acc_mode = left >= it.window ? 0 : (left == it.window - 1 ? 1 : 2);
         pol.ce = it.ce;
         pol.P32 = it.P32;
         pol.r = it.r;
@@ -1309,7 +1523,7 @@ __global__ __launch_bounds__(RX* RY) void k_inner32_batch(const BatchItem32* __r
         pol.phc = it.phc;
         pol.ph2 = it.ph2;
         pol.ph2c = it.ph2c;
-        blocked_body<RX, RY, T>(pol, it.A, it.B, it.g, it.kchunk,
+        blocked_body<RX, RY, T, P::XL>(pol, it.A, it.B, it.g, it.kchunk,
                                 batch_tile<kBlockedStrip>(it, t));
     });
 }
@@ -1320,7 +1534,7 @@ __global__ __launch_bounds__(RX* RY) void k_blocked_batch(const BatchItem* __res
                                                           unsigned int* __restrict__ queue) {
     run_queue(queue, total, [&](int t) {
         const BatchItem& it = items[batch_find(items, nitems, t)];
-        blocked_body<RX, RY, T>(Pol64<CompactCoefs>{compact_view(it.cv)}, it.A, it.B, it.g,
+        blocked_body<RX, RY, T, false>(Pol64<CompactCoefs>{compact_view(it.cv)}, it.A, it.B, it.g,
                                 it.kchunk, batch_tile<kBlockedStrip>(it, t));
     });
 }
@@ -2141,6 +2355,46 @@ __global__ void k_copy(const double2* __restrict__ src, double2* __restrict__ ds
 }
 
 // ---------------------------------------------------------------------------
+// Streaming probe (measurement of the practical HBM ceiling, no THIIM
+// arithmetic): NIN input and NOUT output arrays of n complex128 values with
+// array stride S; out_j = in_j for j < NOUT, the inputs beyond NOUT added to
+// out_0.  The sweeps' access forms: 16-byte buffer loads through a uniform
+// array base and a 32-bit byte offset (each array under 4 GiB), 16-byte
+// non-temporal stores; each thread has 4 values of every input in flight
+// before its first store.  (1, 1) is a plain copy; (13, 12) streams the
+// arrays of one compact-storage sweep pass.
+// ---------------------------------------------------------------------------
+template <int NIN, int NOUT>
+__global__ __launch_bounds__(256) void k_stream_probe(const double2* __restrict__ in,
+                                                      double2* __restrict__ out, long long S,
+                                                      long long n) {
+    constexpr int U = 4;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x; i0 < n;
+         i0 += step * U) {
+        double2 v[NIN][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * step;
+#pragma unroll
+            for (int a = 0; a < NIN; ++a)
+                v[a][u] = i < n ? ldo(in + a * S, 16u * (uint32_t)i) : czero();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * step;
+            if (i >= n) continue;
+            double2 o0 = v[0][u];
+#pragma unroll
+            for (int a = NOUT; a < NIN; ++a) o0 = cadd(o0, v[a][u]);
+            sto(out, 16u * (uint32_t)i, o0);
+#pragma unroll
+            for (int j = 1; j < NOUT; ++j) sto(out + j * S, 16u * (uint32_t)i, v[j][u]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static int grid_1d(long long n, int block) {
@@ -2269,15 +2523,37 @@ hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int rx,
-                                int ry, unsigned int* queue, int ncu, hipStream_t s) {
-    if (nitems < 1 || total < 1 || rx != 32 || ry != 16 || !queue) return hipErrorInvalidValue;
+// the queued launch of a batched complex64 inner pass (left: passes of the
+// step after this one, which sets each item's window-sum mode)
+template <auto K>
+static hipError_t launch_queued_pass(int block, const BatchItem32* items, int nitems, int total,
+                                     int left, unsigned int* queue, int ncu, hipStream_t s) {
+    const long long resident = (long long)blocks_per_cu<K>(block) * (ncu > 0 ? ncu : 256);
+    const int grid = (int)(total < resident ? total : resident);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&items, (void*)&nitems, (void*)&total, (void*)&left, (void*)&queue};
+    e = hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int left,
+                                int max_window, unsigned int* queue, int ncu, hipStream_t s) {
+    if (nitems < 1 || total < 1 || !queue) return hipErrorInvalidValue;
+    const bool acc = left < max_window;  // some item sums this pass
+    if (T == 2 && acc)
+        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32RA>>(1024, items, nitems, total,
+                                                                        left, queue, ncu, s);
     if (T == 2)
-        return launch_queued<k_inner32_batch<32, 16, 2>>(512, items, nitems, total, queue, ncu,
-                                                         s);
+        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32R>>(1024, items, nitems, total,
+                                                                       left, queue, ncu, s);
+    if (T == 3 && acc)
+        return launch_queued_pass<k_inner32_batch<32, 16, 3, Pol32A>>(512, items, nitems, total,
+                                                                       left, queue, ncu, s);
     if (T == 3)
-        return launch_queued<k_inner32_batch<32, 16, 3>>(512, items, nitems, total, queue, ncu,
-                                                         s);
+        return launch_queued_pass<k_inner32_batch<32, 16, 3, Pol32>>(512, items, nitems, total,
+                                                                      left, queue, ncu, s);
     return hipErrorInvalidValue;
 }
 
@@ -2321,6 +2597,8 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
     ap.p.ce = ce;
     ap.p.P32 = P32;
     ap.p.r = nullptr;
+    ap.p.acc = nullptr;
+    ap.p.acc_mode = 0;
     ap.p.S = cv.S;
     ap.p.ph = to32(cv.K.ph);
     ap.p.phc = to32(cv.K.phc);
@@ -2337,6 +2615,8 @@ hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const 
     ap.p.ce = ce;
     ap.p.P32 = P32;
     ap.p.r = nullptr;
+    ap.p.acc = nullptr;
+    ap.p.acc_mode = 0;
     ap.p.S = cv.S;
     ap.p.ph = to32(cv.K.ph);
     ap.p.phc = to32(cv.K.phc);
@@ -2384,18 +2664,39 @@ static hipError_t blocked_impl(const P& pol, const typename P::V* A, typename P:
     return hipGetLastError();
 }
 
-template <class P>
-static hipError_t blocked32_impl(const P& pol, const typename P::V* A, typename P::V* B,
-                                 const Geo& g, int T, int rx, int ry, int kchunk, hipStream_t s) {
+// The complex64 inner passes: two sweeps per pass on 32 x 32 regions
+// (Pol32R), three on 32 x 16 (Pol32).
+static hipError_t blocked32_impl(const Pol32& pol, const float2* A, float2* B, const Geo& g,
+                                 int T, int rx, int ry, int kchunk, hipStream_t s) {
     const int ox = rx - 2 * T, oy = ry - 2 * T;
     if (ox < 1 || oy < 1) return hipErrorInvalidValue;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
-    if (T == 2 && rx == 32 && ry == 16)
-        hipLaunchKernelGGL((k_blocked<32, 16, 2, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
-    else if (T == 3 && rx == 32 && ry == 16)
-        hipLaunchKernelGGL((k_blocked<32, 16, 3, P>), grid, dim3(512), 0, s, pol, A, B, g, kchunk);
-    else
+    const bool acc = pol.acc_mode != 0;
+    if (T == 2 && rx == 32 && ry == 32) {
+        if (acc) {
+            Pol32RA pr;
+            static_cast<Pol32&>(pr) = pol;
+            hipLaunchKernelGGL((k_blocked<32, 32, 2, Pol32RA>), grid, dim3(1024), 0, s, pr, A, B,
+                               g, kchunk);
+        } else {
+            Pol32R pr;
+            static_cast<Pol32&>(pr) = pol;
+            hipLaunchKernelGGL((k_blocked<32, 32, 2, Pol32R>), grid, dim3(1024), 0, s, pr, A, B,
+                               g, kchunk);
+        }
+    } else if (T == 3 && rx == 32 && ry == 16) {
+        if (acc) {
+            Pol32A pa;
+            static_cast<Pol32&>(pa) = pol;
+            hipLaunchKernelGGL((k_blocked<32, 16, 3, Pol32A>), grid, dim3(512), 0, s, pa, A, B, g,
+                               kchunk);
+        } else {
+            hipLaunchKernelGGL((k_blocked<32, 16, 3, Pol32>), grid, dim3(512), 0, s, pol, A, B, g,
+                               kchunk);
+        }
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -2416,10 +2717,13 @@ hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef
 }
 
 hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                          const float2* r, const float2* A, float2* B, const Geo& g, int T,
-                          int rx, int ry, int kchunk, hipStream_t s) {
-    if (!cv.compact) return hipErrorInvalidValue;
+                          const float2* r, const float2* A, float2* B, float2* acc,
+                          int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
+                          hipStream_t s) {
+    if (!cv.compact || (acc_mode && !acc)) return hipErrorInvalidValue;
     Pol32 pol;
+    pol.acc = acc;
+    pol.acc_mode = acc_mode;
     pol.ce = ce;
     pol.P32 = P32;
     pol.r = r;
@@ -2472,6 +2776,18 @@ hipError_t launch_resid(const double2* A, const double2* B, long long S, long lo
                         int c0, double* part, int nblk, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_resid_partial, dim3(nblk), dim3(256), 0, s, A, B, S, N, c0, part);
     hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(const double2* in, double2* out, long long S, long long n,
+                               int nin, int nout, int ncu, hipStream_t s) {
+    const int grid = ncu * 8;  // persistent: 8 workgroups of 256 per CU
+    if (nin == 1 && nout == 1)
+        hipLaunchKernelGGL((k_stream_probe<1, 1>), dim3(grid), dim3(256), 0, s, in, out, S, n);
+    else if (nin == 13 && nout == 12)
+        hipLaunchKernelGGL((k_stream_probe<13, 12>), dim3(grid), dim3(256), 0, s, in, out, S, n);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

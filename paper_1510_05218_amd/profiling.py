@@ -68,8 +68,9 @@ ALG_BYTES_PER_CELL = {
     # side 3 d + 3 r read and 3 d written where the split pairs are symmetric,
     # 5 of each on the PML planes, + the 16 B record: 160 B off the PML, 162
     # at 512^3 with 6-plane PMLs (13 H and 12 E planes not symmetric)
-    "k_blocked<32,16,2,Pol32>": 162,
     "k_blocked<32,16,3,Pol32>": 162,
+    "k_blocked<32,32,2,Pol32R>": 162,
+    "k_inner32_batch<32,32,2,Pol32R>": 162,
 }
 
 
@@ -202,7 +203,7 @@ def run_mixed(n=512):
 
 def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
     """Time to solution on the n^3 benchmark workload (textured, 200 lossless
-    spheres): the mixed solver (T = 3, 2000 inner sweeps per correction) to
+    spheres): the mixed solver (2000 inner sweeps per correction) to
     tol, then the plain FP64 iteration to tol or fp64_budget iterations.  Both
     run in slices so that every slice prints its progress."""
     import time
@@ -217,7 +218,7 @@ def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
     dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
     out = {"grid": f"{n}^3", "tol": tol}
     m = 2000
-    s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=3)
+    s = thiim.Solver(dev, storage="compact", precision="mixed")
     torch.cuda.synchronize()
     t0 = time.time()
     sweeps, r = 0, 1.0
@@ -252,7 +253,7 @@ def run_solve_512(n=512, tol=1e-8, fp64_budget=40000):
 
 
 def run_c3(n=512, tol=1e-8, ref_tol=1e-10, m=2000):
-    """The mixed solver (T = 3, m inner sweeps per correction) on the n^3
+    """The mixed solver (m inner sweeps per correction) on the n^3
     benchmark workload to tol, then the same context on to ref_tol: the
     second iterate is the FP64 fixed point to ref_tol (its residual is the
     FP64 one), and the relative 2-norm difference of the physical fields is
@@ -269,7 +270,7 @@ def run_c3(n=512, tol=1e-8, ref_tol=1e-10, m=2000):
     dev.eps = torch.from_numpy(pb.eps).cuda()
     dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
     out = {"grid": f"{n}^3", "tol": tol, "ref_tol": ref_tol, "inner_sweeps": m}
-    s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=3)
+    s = thiim.Solver(dev, storage="compact", precision="mixed")
     torch.cuda.synchronize()
     t0 = time.time()
     sweeps, r, snap = 0, 1.0, None
@@ -307,7 +308,7 @@ def run_c5(tol=1e-10, m=2000):
 
     pb = inputs.solar_cell(128, 128, 256, seed=20, npml=6, loss_range=(0.1, 0.5))
     w = (pb.eps == pb.layers[1][2]).astype(np.float64)
-    s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=3, adjoint=True)
+    s = thiim.Solver(pb, storage="compact", precision="mixed", adjoint=True)
     torch.cuda.synchronize()
     t0 = time.time()
     rc, n_fw, r = s.solve(tol, 2000000, m)
@@ -352,7 +353,7 @@ def run_spectral(waves_spec="0,1,2:3a:3b:3c", n_wl=32, tol=1e-8, m=2000):
                       for wl in sel]
         cells = sum(p.eps.size for p in probs)
         t0 = time.time()
-        bt = thiim.Batch(probs, precision="mixed", t_block=3)
+        bt = thiim.Batch(probs, precision="mixed")
         res = None
         while res is None or res.max() > tol:
             rc, its, res = bt.solve(tol, 3 * (m + 1), m)

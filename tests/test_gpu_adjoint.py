@@ -191,7 +191,7 @@ def test_adjoint_directional_fd_128x128x256():
     w = (pb.eps == mid).astype(np.float64)  # the middle layer's cells
     assert w.sum() > 0
     m = 2000
-    kw = dict(storage="compact", precision="mixed", t_block=3, adjoint=True)
+    kw = dict(storage="compact", precision="mixed", adjoint=True)
     s = thiim.Solver(pb, **kw)
     rc, n_sw, r = s.solve(1e-10, 2000000, m)
     assert rc == thiim.THIIM_OK, (n_sw, r)
@@ -302,7 +302,7 @@ def test_adjoint_fd_16_cells_128x128x256():
     mid = pb.layers[1][2]
     w = (pb.eps == mid).astype(np.float64)
     m = 2000
-    kw = dict(storage="compact", precision="mixed", t_block=3, adjoint=True)
+    kw = dict(storage="compact", precision="mixed", adjoint=True)
     s = thiim.Solver(pb, **kw)
     rc, n_sw, r = s.solve(1e-10, 2000000, m)
     assert rc == thiim.THIIM_OK, (n_sw, r)

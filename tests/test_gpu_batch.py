@@ -134,21 +134,24 @@ def test_batch_rejects_full_storage_and_duplicates():
     s_c.close()
 
 
-def test_batch_mixed_solve_matches_individual_mixed_solves():
+@pytest.mark.parametrize("t_block", [0, 3])
+def test_batch_mixed_solve_matches_individual_mixed_solves(t_block):
     """With a fixed inner count m above every averaging window, each batched
     problem runs exactly the defect-correction steps of its own mixed solve:
-    same sweep counts, same residuals, bit-identical fields."""
+    same sweep counts, same residuals, bit-identical fields (two sweeps per
+    inner pass on 32 x 32 regions, and three on 32 x 16)."""
     _require_gpu()
+    print(f"[batch mixed] t_block={t_block}", flush=True)
     probs = [inputs.random_problem(12, 10, 16, seed=81, all_sources=False),
              inputs.random_problem(20, 14, 12, seed=82, all_sources=False, omega=0.5),
              inputs.random_problem(9, 9, 20, seed=83, all_sources=False, bcx=1),
              inputs.random_problem(40, 33, 10, seed=84, all_sources=False, omega=0.2)]
     tol, m = 1e-9, 300
-    bt = thiim.Batch(probs, precision="mixed", t_block=3)
+    bt = thiim.Batch(probs, precision="mixed", t_block=t_block)
     rc, its, res = bt.solve(tol, 400000, m)
     assert rc == thiim.THIIM_OK, (its, res)
     for i, pb in enumerate(probs):
-        s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=3)
+        s = thiim.Solver(pb, storage="compact", precision="mixed", t_block=t_block)
         rc1, it1, r1 = s.solve(tol, 400000, m)
         assert rc1 == thiim.THIIM_OK
         assert it1 == its[i] and r1 == res[i], (i, it1, its[i], r1, res[i])
@@ -162,7 +165,7 @@ def test_batch_mixed_adaptive_reaches_tolerance():
     probs = [inputs.solar_cell(24, 24, 36, seed=s, npml=6, loss_range=(0.1, 0.5),
                                wavelength_nm=wl)
              for s, wl in ((10, 400.0), (11, 700.0), (12, 1000.0))]
-    bt = thiim.Batch(probs, precision="mixed", t_block=3)
+    bt = thiim.Batch(probs, precision="mixed")
     rc, its, res = bt.solve(1e-8, 400000, 0)
     assert rc == thiim.THIIM_OK and np.all(res <= 1e-8), (its, res)
     # the FP64 residual recomputed from scratch agrees
