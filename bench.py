@@ -30,8 +30,11 @@ generator where plain FP64 does reach 1e-8 (``solve_1e-8_small``), and a
 batched spectral sweep (batched against one-by-one throughput, and the
 batched mixed solver against plain FP64 in solves/s).
 
-The roofline entry also carries the bandwidth of a plain 4 GiB device copy
-measured in the same process (``copy_gbs``) and the sweep's fractions of it,
+The roofline entry also carries the practical HBM ceiling measured in the
+same process by the library's streaming probe (``copy_gbs``: a 2 GiB copy
+with the sweeps' load and store forms; ``stream_13x12_gbs``: the 13 input
+and 12 output arrays of one compact-storage pass, streamed without
+arithmetic; torch's own copy for reference) and the sweep's fractions of it,
 the counter bandwidth when ``traffic`` is known, and the GLUP/s over the
 roofline of the naive sweep on the paper's layout (8 TB/s / 1024 B per
 lattice update), which temporal blocking can exceed.
@@ -66,14 +69,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_thiim_512cubed.json")
 #     naive:   H sweep 12 t/c + 6 H + 6 E read, 6 H written = 480 B, E sweep
 #              the same -> 960 B
 #     fused:   24 t/c + 12 fields read, 12 written = 768 B
-#     blocked: one pass for 2 iterations reads 24 t/c + 12 fields and writes
-#              12 = 768 B per pass -> 384 B
+#     blocked: one pass for 2 iterations reads 12 fields and the 24 t/c of
+#              each stage's planes (48 t/c: a column's coefficients cannot
+#              stay on chip between its two stages) and writes 12 = 1152 B
+#              per pass -> 576 B
 #   compact storage (eps per cell):
 #     naive:   H sweep 12 read + 6 written = 288 B, E sweep 13 + 6 = 304 B
 #     fused:   eps + 12 fields read, 12 written = 400 B
 #     blocked: 400 B per two-iteration pass -> 200 B
 BYTES_PER_LUP = {
-    ("naive", "full"): 960, ("fused", "full"): 768, ("blocked", "full"): 384,
+    ("naive", "full"): 960, ("fused", "full"): 768, ("blocked", "full"): 576,
     ("naive", "compact"): 592, ("fused", "compact"): 400, ("blocked", "compact"): 200,
 }
 ITERS_PER_LAUNCH = {"naive": 0.5, "fused": 1, "blocked": 2}
@@ -86,8 +91,8 @@ SWEEP_KERNEL = {
     ("blocked", "compact"): "k_blocked<32,16,2,Pol64<CompactCoefs>>",
 }
 ADJ_BYTES_PER_LUP = 448  # transposed sweep: 12 lam + eps + 3 g read, 12 written
-CONTEXT_VARIANTS = [("naive", "full"), ("fused", "full"), ("naive", "compact"),
-                    ("fused", "compact")]
+CONTEXT_VARIANTS = [("naive", "full"), ("fused", "full"), ("blocked", "full"),
+                    ("naive", "compact"), ("fused", "compact")]
 
 
 def log(*a):
@@ -229,6 +234,34 @@ def oracle_timing():
         if not light:
             del coef
     return out
+
+
+def probe_bandwidth(torch, thiim, nin, nout, n):
+    """The library's streaming probe (thiim_stream_probe: the sweeps' 16-byte
+    buffer loads and non-temporal stores, no arithmetic) over nin input and
+    nout output arrays of n complex128 values: median of five launches, GB/s
+    counting every byte read and written."""
+    src = torch.ones((nin, n, 2), dtype=torch.float64, device="cuda")
+    dst = torch.empty((nout, n, 2), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def run():
+        thiim.thiim_stream_probe(src.data_ptr(), dst.data_ptr(), n, n, nin, nout, st.cuda_stream)
+
+    run()
+    ts = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        run()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    ts.sort()
+    return (nin + nout) * 16 * n / (ts[2] * 1e-3) / 1e9
 
 
 def copy_bandwidth(torch):
@@ -530,8 +563,11 @@ def main():
     bytes_per_launch = BYTES_PER_LUP[head] * N * ipl
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     traffic = traffic_for(SWEEP_KERNEL[head], N)
-    copy_gbs = copy_bandwidth(torch)
-    log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
+    torch_copy_gbs = copy_bandwidth(torch)
+    copy_gbs = probe_bandwidth(torch, thiim, 1, 1, 2 ** 27)
+    stream_gbs = probe_bandwidth(torch, thiim, 13, 12, 2 ** 25)
+    log(f"[bench] streaming probe: copy {copy_gbs:.0f} GB/s, 13 in + 12 out {stream_gbs:.0f} GB/s "
+        f"(torch copy {torch_copy_gbs:.0f} GB/s)")
     kernels = {}
     for (k, st), (sm, im, r) in results.items():
         ms = sum(im) / len(im)
@@ -586,13 +622,22 @@ def main():
                      "traffic": traffic,
                      "alg_bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "stream_13x12_gbs": stream_gbs, "torch_copy_gbs": torch_copy_gbs,
                      "counter_gbs": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
                      "counter_frac": None if traffic is None
                      else traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "counter_frac_of_copy": None if traffic is None
                      else traffic / (launch_ms * 1e-3) / 1e9 / copy_gbs,
+                     "counter_frac_of_stream": None if traffic is None
+                     else traffic / (launch_ms * 1e-3) / 1e9 / stream_gbs,
+                     # GLUP/s over the roofline of the naive sweep: on the
+                     # paper's layout (1024 B/LUP), and on the same storage
+                     # (the naive sweep's bytes of this storage), which
+                     # isolates the gain of temporal blocking
                      "glups_over_naive_roofline": N / (it_ms * 1e-3) / 1e9
-                     / (HBM_PEAK_GBS / 1024.0)},
+                     / (HBM_PEAK_GBS / 1024.0),
+                     "glups_over_naive_roofline_same_storage": N / (it_ms * 1e-3) / 1e9
+                     / (HBM_PEAK_GBS / BYTES_PER_LUP[("naive", args.storage)])},
         "cpu_baseline": cpu,
         "kernels": kernels,
         "solve_1e-8": solve,

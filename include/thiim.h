@@ -312,6 +312,20 @@ int thiim_set_fields(thiim_ctx *ctx, const double *src);
  * the compact storage when that is in use.  Synchronising. */
 int thiim_get_coeffs(thiim_ctx *ctx, double *dst);
 
+/* ---- measurement ------------------------------------------------------- */
+
+/* Streaming probe of the practical HBM bandwidth, with the sweeps' access
+ * forms (16-byte buffer loads, non-temporal 16-byte stores) and no THIIM
+ * arithmetic: nin input arrays of n complex128 values at src (array stride
+ * `stride` values) and nout output arrays at dst (same stride);
+ * out_j = in_j for j < nout, the inputs beyond nout added into out_0.
+ * (nin, nout) = (1, 1) is a plain copy, (13, 12) streams the arrays of one
+ * compact-storage sweep pass (eps and 12 fields in, 12 fields out).  Device
+ * buffers, 16-byte aligned, each array under 4 GiB.  Enqueued on `stream`
+ * (a hipStream_t); asynchronous. */
+int thiim_stream_probe(const double *src, double *dst, long long n, long long stride, int nin,
+                       int nout, void *stream);
+
 /* Iterations done since create / set_fields. */
 int thiim_iterations(const thiim_ctx *ctx, long long *n);
 

@@ -50,6 +50,7 @@ struct Layout {
     size_t off_a, off_b;
     size_t off_r32, off_d32;  // mixed precision: 12 + 24 complex64 arrays
     size_t off_acc32;         // mixed precision: 12 complex64 arrays (window sum)
+    size_t off_rt32;          // mixed precision: 12 complex64 arrays (r_T)
     size_t off_ce, off_p32;   // mixed precision: per-cell float4 records, nz plane rows
     size_t off_lam, off_g;    // adjoint: 4 x 12 + 3 complex128 arrays
     size_t total;
@@ -72,13 +73,15 @@ Layout layout_of(const thiim_grid* g) {
     off += (size_t)12 * L.S * 16;
     L.off_b = off;
     off += (size_t)12 * L.S * 16;
-    L.off_r32 = L.off_d32 = L.off_acc32 = L.off_ce = L.off_p32 = 0;
+    L.off_r32 = L.off_d32 = L.off_acc32 = L.off_rt32 = L.off_ce = L.off_p32 = 0;
     if (g->precision == THIIM_PRECISION_MIXED) {
         L.off_r32 = off;
         off += (size_t)12 * L.S * 8;
         L.off_d32 = off;
         off += (size_t)24 * L.S * 8;
         L.off_acc32 = off;
+        off += (size_t)12 * L.S * 8;
+        L.off_rt32 = off;
         off += (size_t)12 * L.S * 8;
         L.off_ce = off;
         off += (size_t)L.S * 16;
@@ -167,6 +170,7 @@ struct thiim_ctx {
     float2* r32;                                // mixed precision buffers
     float2* d32[2];
     float2* acc32;                // window sum of the inner passes
+    float2* rt32;                 // r_T = (I + M) r, the two-sweep passes' source
     float4* ce32;                 // per-cell complex64 E-coefficient records
     thiim::PlaneCoef32* p32;      // per-plane complex64 H coefficients
     int inner_t, inner_rx, inner_ry, inner_chunk;
@@ -343,6 +347,7 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     c->d32[0] = L.off_d32 ? (float2*)(c->ws + L.off_d32) : nullptr;
     c->d32[1] = L.off_d32 ? c->d32[0] + 12 * L.S : nullptr;
     c->acc32 = L.off_acc32 ? (float2*)(c->ws + L.off_acc32) : nullptr;
+    c->rt32 = L.off_rt32 ? (float2*)(c->ws + L.off_rt32) : nullptr;
     c->ce32 = L.off_ce ? (float4*)(c->ws + L.off_ce) : nullptr;
     c->p32 = L.off_p32 ? (thiim::PlaneCoef32*)(c->ws + L.off_p32) : nullptr;
     c->lam[0] = L.off_lam ? (double2*)(c->ws + L.off_lam) : nullptr;
@@ -502,6 +507,26 @@ constexpr int kMaxInner = 1 << 15;
 // bound).
 constexpr double kGrowth = 1e6;
 
+// One inner pass of the context from A into B: with two sweeps per pass the
+// source is r_T (rt32) at the last stage, with three r (r32) at every stage.
+hipError_t launch_pass32(thiim_ctx* c, const float2* A, float2* B, int acc_mode, hipStream_t s) {
+    const bool last = c->inner_t == 2;
+    return thiim::launch_inner32(c->cv, c->ce32, c->p32, last ? c->rt32 : c->r32, last, A, B,
+                                 c->acc32, acc_mode, c->geo, c->inner_t, c->inner_rx,
+                                 c->inner_ry, c->inner_chunk, s);
+}
+
+// r_T = (I + M) r for the two-sweep passes: one pass with source r at both
+// stages from d = 0 (d32[1] cleared first).  Nothing for three-sweep passes.
+hipError_t launch_rt(thiim_ctx* c, hipStream_t s) {
+    if (c->inner_t != 2) return hipSuccess;
+    hipError_t e = thiim::launch_fill_zero((double2*)c->d32[1], 6 * c->L.S, s);
+    if (e != hipSuccess) return e;
+    return thiim::launch_inner32(c->cv, c->ce32, c->p32, c->r32, false, c->d32[1], c->rt32,
+                                 nullptr, 0, c->geo, 2, c->inner_rx, c->inner_ry,
+                                 c->inner_chunk, s);
+}
+
 int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, double* rel_res) {
     const int other = 1 - c->cur;
     const int T = c->inner_t;
@@ -538,14 +563,13 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
         // complex64: d = r, then passes of d <- M d + r; the last Kp averaged
         int passes = (m - 1 + T - 1) / T;
         if (passes < Kp) passes = Kp;
-        e = thiim::launch_copy32(c->r32, c->d32[0], c->L.S, c->L.N, c->stream);
+        e = launch_rt(c, c->stream);
+        if (e == hipSuccess) e = thiim::launch_copy32(c->r32, c->d32[0], c->L.S, c->L.N, c->stream);
         int di = 0;
         for (int p = 0; e == hipSuccess && p < passes; ++p) {
             // the last Kp passes also sum what they store into acc32
             const int acc_mode = p < passes - Kp ? 0 : (p == passes - Kp ? 1 : 2);
-            e = thiim::launch_inner32(c->cv, c->ce32, c->p32, c->r32, c->d32[di],
-                                      c->d32[1 - di], c->acc32, acc_mode, c->geo, T,
-                                      c->inner_rx, c->inner_ry, c->inner_chunk, c->stream);
+            e = launch_pass32(c, c->d32[di], c->d32[1 - di], acc_mode, c->stream);
             di = 1 - di;
         }
         // x += (window sum) / Kp in FP64
@@ -1235,6 +1259,7 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                         it.ph2c = make_float2((float)c->cv.K.ph2c.x, (float)c->cv.K.ph2c.y);
                         it.A = c->d32[par];
                         it.B = c->d32[1 - par];
+                        it.rT = c->rt32;
                         it.acc = c->acc32;
                         it.window = Kp[i];
                         it.g = c->geo;
@@ -1265,10 +1290,12 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                     const int pi = std::max((m - 1 + gr.T - 1) / gr.T, Kp[i]);
                     P = std::max(P, pi);
                 }
-                for (int i : gr.members)
+                for (int i : gr.members) {
+                    if (err == hipSuccess) err = launch_rt(b->ctx[i], b->stream);
                     if (err == hipSuccess)
                         err = thiim::launch_copy32(b->ctx[i]->r32, b->ctx[i]->d32[0],
                                                    b->ctx[i]->L.S, b->ctx[i]->L.N, b->stream);
+                }
                 // each item sums its last Kp passes into its acc32
                 int wmax = 0;
                 for (int i : gr.members) wmax = std::max(wmax, Kp[i]);
@@ -1612,6 +1639,20 @@ void thiim_batch_destroy(thiim_batch* b) {
         g_scratch_busy[b->static_dev] = false;
     }
     delete b;
+}
+
+int thiim_stream_probe(const double* src, double* dst, long long n, long long stride, int nin,
+                       int nout, void* stream) {
+    if (!src || !dst || n < 1 || stride < n)
+        return fail(THIIM_EINVAL, "stream probe: need src, dst, n >= 1 and stride >= n");
+    if (!((nin == 1 && nout == 1) || (nin == 13 && nout == 12)))
+        return fail(THIIM_EINVAL, "stream probe: (nin, nout) must be (1, 1) or (13, 12)");
+    if (n * 16 > 0xFFFFFFFFLL) return fail(THIIM_EINVAL, "stream probe: arrays must be < 4 GiB");
+    if ((uintptr_t)src % 16 || (uintptr_t)dst % 16)
+        return fail(THIIM_EINVAL, "stream probe: buffers must be 16-byte aligned");
+    hipError_t e = thiim::launch_stream_probe((const double2*)src, (double2*)dst, stride, n, nin,
+                                              nout, cu_count(), (hipStream_t)stream);
+    return e == hipSuccess ? THIIM_OK : hip_fail(e, "stream probe launch");
 }
 
 int thiim_iterations(const thiim_ctx* c, long long* n) {

@@ -76,6 +76,7 @@ struct BatchItem32 {
     float2 ph, phc, ph2, ph2c;
     const float2* A;
     float2* B;
+    const float2* rT;  // last-stage source of the two-sweep passes
     float2* acc;  // window sum of the correction (pair-sum form)
     int window;   // passes in the window: the last `window` passes of a step
     Geo g;
@@ -111,13 +112,14 @@ hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, cons
 // per-plane H table (once per context), then inner sweeps d <- M d + r.
 hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef32* P32,
                          hipStream_t s);
-// One complex64 inner pass d <- M d + r (T sweeps: T = 2 on 32 x 32 regions,
-// T = 3 on 32 x 16), adding the stored d to acc with acc_mode 1 (acc = d) or
-// 2 (acc += d).
+// One complex64 inner pass of T sweeps d <- M d + r (T = 2 on 32 x 32 regions,
+// T = 3 on 32 x 16), or with src_last (T = 2) d <- M^T d + r with r added at
+// the last stage only (r then holds r_T = (I + M) r of the sweep source),
+// adding the stored d to acc with acc_mode 1 (acc = d) or 2 (acc += d).
 hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                          const float2* r, const float2* A, float2* B, float2* acc,
-                          int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
-                          hipStream_t s);
+                          const float2* r, bool src_last, const float2* A, float2* B,
+                          float2* acc, int acc_mode, const Geo& g, int T, int rx, int ry,
+                          int kchunk, hipStream_t s);
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
                          long long S, long long N, long long nxy, double* part, int nblk,
                          double* out, hipStream_t s);

@@ -411,6 +411,7 @@ struct Pol64 {
     using V = double2;
     static constexpr int MIN_WAVES = 0;  // no occupancy request
     static constexpr bool XL = false;    // neighbour sums through LDS
+    static constexpr bool SRC_LAST = false;
     static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
     static constexpr bool H_SRC_AFTER = false;
     static constexpr bool CARRY = false;
@@ -485,6 +486,7 @@ struct Pol32 {
     using CRec = float4;
     static constexpr int MIN_WAVES = 0;
     static constexpr bool XL = false;
+    static constexpr bool SRC_LAST = false;
     static constexpr int HMASK = 0, EMASK = SRC_MASK_ALL;
     static constexpr bool H_SRC_AFTER = true;
     // sources and the E-coefficient record are loaded once, by the first
@@ -627,6 +629,19 @@ struct Pol32R : Pol32 {
         ecoef_c(k, load_crec(po, bo), t, c);
         load_e_src(k, po, bo, src);
     }
+    __device__ __forceinline__ void ecoef_nosrc(int k, long long po, uint32_t bo, V t[6],
+                                                V c[6]) const {
+        ecoef_c(k, load_crec(po, bo), t, c);
+    }
+};
+
+// Pol32R with the source added at the last stage only: a pass of T sweeps
+// of d <- M d + r equals d <- M^T d + r_T with r_T = (I + M + ... + M^{T-1}) r,
+// and the pass reads r_T (the policy's r) once, for the last stage's planes,
+// instead of r at every stage.  r_T is one pass of Pol32R from d = 0 with
+// source r.
+struct Pol32L : Pol32R {
+    static constexpr bool SRC_LAST = true;
 };
 
 // The same passes that also sum what they store into the window sum acc (the
@@ -647,6 +662,7 @@ struct WithAcc : Base {
 };
 using Pol32A = WithAcc<Pol32>;
 using Pol32RA = WithAcc<Pol32R>;
+using Pol32LA = WithAcc<Pol32L>;
 
 // Coefficient data of the complex64 inner sweeps, built once per context.
 // Per cell: {+-r0, r1, b0, b1} with r_i = 1/d_i the real factor of t and c in
@@ -1281,10 +1297,20 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 nb.ex_zm = cadd(zp[0], zp[1]);
                 nb.ey_zm = cadd(zp[2], zp[3]);
                 V t[6], c[6], src[6];
+                // SRC_LAST policies: the source enters at the last stage only
+                const bool with_src = !P::SRC_LAST || s == T;
                 if constexpr (P::CARRY) {
                     pol.hcoef_c(kh, t, c);
 #pragma unroll
                     for (int q = 0; q < 6; ++q) src[q] = rHq[s - 1][q];
+                } else if constexpr (P::SRC_LAST) {
+                    if (with_src) {
+                        pol.hcoef(kh, po, bo, t, c, src);
+                    } else {
+                        pol.hcoef_c(kh, t, c);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) src[q] = vzero<V>();
+                    }
                 } else {
                     pol.hcoef(kh, po, bo, t, c, src);
                 }
@@ -1292,7 +1318,7 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                 hsum[0] = cadd(h[0], h[1]);
                 hsum[1] = cadd(h[2], h[3]);
                 hsum[2] = cadd(h[4], h[5]);
-                if (P::H_SRC_AFTER) {
+                if (P::H_SRC_AFTER && with_src) {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) h[q] = cadd(h[q], src[q]);
                 }
@@ -1358,16 +1384,28 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
 #pragma unroll
                 for (int q = 0; q < 6; ++q) e[q] = (s == 1) ? e0p[q] : ep[s - 1][q];
                 V t[6], c[6], src[6];
+                const bool with_src = !P::SRC_LAST || s == T;
                 if constexpr (P::CARRY) {
                     pol.ecoef_c(ke, crq[s - 1], t, c);
 #pragma unroll
                     for (int q = 0; q < 6; ++q) src[q] = rEq[s - 1][q];
                 } else if constexpr (P::CARRY_REC) {
                     pol.ecoef_rec(ke, crq[s - 1], po, bo, t, c, src);
+                } else if constexpr (P::SRC_LAST) {
+                    if (with_src) {
+                        pol.ecoef(ke, po, bo, t, c, src);
+                    } else {
+                        pol.ecoef_nosrc(ke, po, bo, t, c);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) src[q] = vzero<V>();
+                    }
                 } else {
                     pol.ecoef(ke, po, bo, t, c, src);
                 }
-                update_e_t<P::EMASK>(e, t, c, src, hb);
+                if (with_src)
+                    update_e_t<P::EMASK>(e, t, c, src, hb);
+                else
+                    update_e_t<0>(e, t, c, src, hb);
                 if (s == T && own && ke >= k0 && ke < k1) pol.store_e(BE, S, ke, po, bo, e);
             }
 #pragma unroll
@@ -1517,7 +1555,7 @@ __global__ __launch_bounds__(RX* RY, (P::MIN_WAVES > 0 ? P::MIN_WAVES : 1)) void
         pol.acc_mode = left >= it.window ? 0 : (left == it.window - 1 ? 1 : 2);
         pol.ce = it.ce;
         pol.P32 = it.P32;
-        pol.r = it.r;
+        pol.r = P::SRC_LAST ? it.rT : it.r;
         pol.S = it.S;
         pol.ph = it.ph;
         pol.phc = it.phc;
@@ -2542,11 +2580,12 @@ hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total,
                                 int max_window, unsigned int* queue, int ncu, hipStream_t s) {
     if (nitems < 1 || total < 1 || !queue) return hipErrorInvalidValue;
     const bool acc = left < max_window;  // some item sums this pass
+    // two-sweep passes read the items' r_T (last-stage source)
     if (T == 2 && acc)
-        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32RA>>(1024, items, nitems, total,
+        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32LA>>(1024, items, nitems, total,
                                                                         left, queue, ncu, s);
     if (T == 2)
-        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32R>>(1024, items, nitems, total,
+        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32L>>(1024, items, nitems, total,
                                                                        left, queue, ncu, s);
     if (T == 3 && acc)
         return launch_queued_pass<k_inner32_batch<32, 16, 3, Pol32A>>(512, items, nitems, total,
@@ -2667,24 +2706,27 @@ static hipError_t blocked_impl(const P& pol, const typename P::V* A, typename P:
 // The complex64 inner passes: two sweeps per pass on 32 x 32 regions
 // (Pol32R), three on 32 x 16 (Pol32).
 static hipError_t blocked32_impl(const Pol32& pol, const float2* A, float2* B, const Geo& g,
-                                 int T, int rx, int ry, int kchunk, hipStream_t s) {
+                                 int T, int rx, int ry, bool src_last, int kchunk,
+                                 hipStream_t s) {
     const int ox = rx - 2 * T, oy = ry - 2 * T;
     if (ox < 1 || oy < 1) return hipErrorInvalidValue;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
     const bool acc = pol.acc_mode != 0;
+    auto launch2 = [&](auto pr) {
+        static_cast<Pol32&>(pr) = pol;
+        hipLaunchKernelGGL((k_blocked<32, 32, 2, decltype(pr)>), grid, dim3(1024), 0, s, pr, A,
+                           B, g, kchunk);
+    };
     if (T == 2 && rx == 32 && ry == 32) {
-        if (acc) {
-            Pol32RA pr;
-            static_cast<Pol32&>(pr) = pol;
-            hipLaunchKernelGGL((k_blocked<32, 32, 2, Pol32RA>), grid, dim3(1024), 0, s, pr, A, B,
-                               g, kchunk);
-        } else {
-            Pol32R pr;
-            static_cast<Pol32&>(pr) = pol;
-            hipLaunchKernelGGL((k_blocked<32, 32, 2, Pol32R>), grid, dim3(1024), 0, s, pr, A, B,
-                               g, kchunk);
-        }
-    } else if (T == 3 && rx == 32 && ry == 16) {
+        if (src_last && acc)
+            launch2(Pol32LA{});
+        else if (src_last)
+            launch2(Pol32L{});
+        else if (acc)
+            launch2(Pol32RA{});
+        else
+            launch2(Pol32R{});
+    } else if (T == 3 && rx == 32 && ry == 16 && !src_last) {
         if (acc) {
             Pol32A pa;
             static_cast<Pol32&>(pa) = pol;
@@ -2717,9 +2759,9 @@ hipError_t launch_prep32(const CoefView& cv, const Geo& g, float4* ce, PlaneCoef
 }
 
 hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                          const float2* r, const float2* A, float2* B, float2* acc,
-                          int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
-                          hipStream_t s) {
+                          const float2* r, bool src_last, const float2* A, float2* B,
+                          float2* acc, int acc_mode, const Geo& g, int T, int rx, int ry,
+                          int kchunk, hipStream_t s) {
     if (!cv.compact || (acc_mode && !acc)) return hipErrorInvalidValue;
     Pol32 pol;
     pol.acc = acc;
@@ -2732,7 +2774,7 @@ hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef3
     pol.phc = to32(cv.K.phc);
     pol.ph2 = to32(cv.K.ph2);
     pol.ph2c = to32(cv.K.ph2c);
-    return blocked32_impl(pol, A, B, g, T, rx, ry, kchunk, s);
+    return blocked32_impl(pol, A, B, g, T, rx, ry, src_last, kchunk, s);
 }
 
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
@@ -2781,7 +2823,11 @@ hipError_t launch_resid(const double2* A, const double2* B, long long S, long lo
 
 hipError_t launch_stream_probe(const double2* in, double2* out, long long S, long long n,
                                int nin, int nout, int ncu, hipStream_t s) {
-    const int grid = ncu * 8;  // persistent: 8 workgroups of 256 per CU
+    // one pass over the data: every thread moves 4 values of each array (a
+    // persistent grid of 8 workgroups per CU measured 10-15% slower)
+    (void)ncu;
+    const long long gl = (n + 256LL * 4 - 1) / (256LL * 4);
+    const int grid = (int)(gl < 2147483647LL ? gl : 2147483647LL);
     if (nin == 1 && nout == 1)
         hipLaunchKernelGGL((k_stream_probe<1, 1>), dim3(grid), dim3(256), 0, s, in, out, S, n);
     else if (nin == 13 && nout == 12)

@@ -8,6 +8,8 @@
   ``bench.py --calib-copy``).  The result records a hash of the kernel
   sources; ``bench.py`` reports the traffic only while that hash matches.
 
+* ``run_kernels``: the workload of the counter runs -- every sweep kernel on
+  the n^3 benchmark problem from a dense random state.
 * ``run_mixed``: a GPU workload for profiling the complex64 inner sweeps --
   two defect-correction steps of the mixed-precision solver on the n^3
   benchmark problem, with T = 2 and with T = 3 inner passes.
@@ -22,6 +24,7 @@
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD [NAME,NAME...]
+    python -m paper_1510_05218_amd.profiling run_kernels [n]
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
     python -m paper_1510_05218_amd.profiling run_c3 [n]
@@ -51,7 +54,8 @@ ALG_BYTES_PER_CELL = {
     "k_naive_e<CompactCoefs>": 304,          # + eps
     "k_fused<64,8,FullCoefs>": 768,          # 24 t/c + 12 read, 12 written
     "k_fused<64,8,CompactCoefs>": 400,       # eps + 12 read, 12 written
-    "k_blocked<64,8,2,Pol64<FullCoefs>>": 768,
+    # full storage: each stage reads its planes' 24 t/c arrays
+    "k_blocked<64,8,2,Pol64<FullCoefs>>": 1152,
     "k_blocked<32,16,2,Pol64<CompactCoefs>>": 400,
     "k_blocked<64,8,2,Pol64<CompactCoefs>>": 400,
     # transposed sweep: 12 lam + eps + 3 g read, 12 written
@@ -175,6 +179,60 @@ def kernel_stats_md(stats_csv, n_cells, out_md, command, only=None):
                      f"{float(r['MaxNs']) / 1e6:.3f} | {b if b else '-'} | {gbs} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def run_kernels(n=512, m=180):
+    """Workload of the counter runs: a calibration copy of 4 GiB, then every
+    sweep kernel on the n^3 benchmark problem from a dense state (unit-variance random fields, so that no part
+    of the grid holds zeros), a few launches each -- the FP64 naive, fused
+    and blocked sweeps on compact and on the 28-array storage, then one
+    mixed-precision correction (m inner sweeps) with two- and with
+    three-sweep inner passes.  Prints one line per block."""
+    import torch
+
+    from . import inputs, thiim
+
+    # the counters' calibration: a plain copy of CALIB_BYTES (read and written)
+    a = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    pb = inputs.solar_cell(n, n, n, seed=3, npml=6, n_spheres=200 if n >= 128 else 0)
+    dev = inputs.Problem(**{**pb.__dict__})
+    dev.eps = torch.from_numpy(pb.eps).cuda()
+    dev.sources = {k: torch.from_numpy(v).cuda() for k, v in pb.sources.items()}
+
+    def dense(s):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(5)
+        shape = (12, n, n, n)
+        x = torch.complex(torch.randn(shape, dtype=torch.float64, device="cuda", generator=g),
+                          torch.randn(shape, dtype=torch.float64, device="cuda", generator=g))
+        s.set_fields(x)
+        del x
+        torch.cuda.empty_cache()
+
+    for storage in ("compact", "full"):
+        for kernel, its in (("naive", 2), ("fused", 4), ("blocked", 8)):
+            s = thiim.Solver(dev, storage=storage, kernel=kernel)
+            dense(s)
+            s.iterate(its)
+            torch.cuda.synchronize()
+            s.close()
+            torch.cuda.empty_cache()
+            print(json.dumps({"storage": storage, "kernel": kernel, "iterations": its}),
+                  flush=True)
+    for t_block in (0, 3):
+        s = thiim.Solver(dev, storage="compact", precision="mixed", t_block=t_block)
+        dense(s)
+        s.solve(1e-30, 1 + m, m)
+        torch.cuda.synchronize()
+        s.close()
+        torch.cuda.empty_cache()
+        print(json.dumps({"mixed_t_block": t_block, "inner_sweeps": m}), flush=True)
 
 
 def run_mixed(n=512):
@@ -381,6 +439,8 @@ def main(argv):
         stats, n, out, cmd = argv[1:5]
         kernel_stats_md(stats, int(n), out, cmd, argv[5] if len(argv) > 5 else None)
         print(open(out).read())
+    elif argv[0] == "run_kernels":
+        run_kernels(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_mixed":
         run_mixed(int(argv[1]) if len(argv) > 1 else 512)
     elif argv[0] == "run_solve":

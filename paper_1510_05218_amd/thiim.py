@@ -34,7 +34,7 @@ SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_adjoint_grad", "thiim_autotune", "thiim_batch_workspace_bytes",
            "thiim_batch_create", "thiim_batch_iterate", "thiim_batch_residual",
            "thiim_batch_solve", "thiim_batch_autotune", "thiim_batch_destroy",
-           "thiim_batch_create_static",
+           "thiim_batch_create_static", "thiim_stream_probe",
            "thiim_destroy",
            "thiim_last_error", "thiim_status_str")
 
@@ -101,6 +101,8 @@ def lib():
         L.thiim_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
         L.thiim_batch_create.argtypes = [P(vp), i, vp, ctypes.c_size_t, P(vp)]
         L.thiim_batch_create_static.argtypes = [P(vp), i, P(vp)]
+        L.thiim_stream_probe.argtypes = [vp, vp, ctypes.c_longlong, ctypes.c_longlong, i, i,
+                                         vp]
         L.thiim_batch_iterate.argtypes = [vp, i]
         L.thiim_batch_residual.argtypes = [vp, P(d)]
         L.thiim_batch_solve.argtypes = [vp, d, i, i, P(i), P(d)]
@@ -226,6 +228,13 @@ def thiim_batch_create_static(ctxs):
     out = ctypes.c_void_p()
     _check(lib().thiim_batch_create_static(arr, len(ctxs), ctypes.byref(out)))
     return out
+
+
+def thiim_stream_probe(src_ptr: int, dst_ptr: int, n: int, stride: int, nin: int, nout: int,
+                       stream_ptr: int):
+    _check(lib().thiim_stream_probe(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(n),
+                                    int(stride), int(nin), int(nout),
+                                    ctypes.c_void_p(stream_ptr)))
 
 
 def thiim_batch_iterate(batch, n: int):
