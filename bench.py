@@ -56,6 +56,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -471,6 +473,61 @@ def spectral_context(torch, thiim, inputs, tol=1e-8):
     return out
 
 
+def spectral_wave_context(torch, thiim, inputs, tol=1e-8):
+    """One resident wave of the full spectral configuration: all four of its
+    geometries (64^3, 96 x 96 x 128, 128 x 128 x 256, 192 x 192 x 384; seeds
+    10-13, eps'' in [0, 0.5]) at the two end wavelengths, 300 and 1100 nm
+    (8 problems, 39.6 M cells).  (1) FP64 iteration with the batch tuned per
+    grid against one configuration for all (thiim_batch_autotune times both);
+    (2) the batched mixed-precision solve to tol; (3) plain FP64 batched for
+    the same wall time, reporting how many problems it solved."""
+    geoms = [(64, 64, 64, 10), (96, 96, 128, 11), (128, 128, 256, 12), (192, 192, 384, 13)]
+    wls = [300.0, 1100.0]
+    probs = [inputs.solar_cell(nx, ny, nz, seed=sd, npml=6, wavelength_nm=wl)
+             for nx, ny, nz, sd in geoms for wl in wls]
+    cells = sum(p.eps.size for p in probs)
+    out = {"problems": len(probs), "cells": cells, "wavelengths_nm": wls,
+           "grids": [f"{nx}x{ny}x{nz}" for nx, ny, nz, _ in geoms], "tol": tol}
+    bt = thiim.Batch(probs, autotune=True)
+    t = bt.tuning
+    out["batch_tuning"] = {"one_for_all_ms_per_iteration": t["one_for_all_ms"],
+                           "per_grid_ms_per_iteration": t["per_grid_ms"],
+                           "per_grid_kept": bool(t["per_grid"]),
+                           "one_for_all": {k: t[k] for k in ("kernel", "tile_x", "tile_y",
+                                                             "z_chunk")}}
+    out["batched_fp64_glups"] = cells / (t["ms_per_iteration"] * 1e-3) / 1e9
+    bt.close()
+    torch.cuda.empty_cache()
+    log(f"[bench] spectral wave: one for all {t['one_for_all_ms']:.2f} ms, per grid "
+        f"{t['per_grid_ms']:.2f} ms per iteration")
+    t0 = time.perf_counter()
+    bt = thiim.Batch(probs, precision="mixed")
+    rc, its, res = bt.solve(tol, 4000000, 0)
+    bt.synchronize()
+    dt = time.perf_counter() - t0
+    bt.close()
+    torch.cuda.empty_cache()
+    out["batched_mixed"] = {"status": thiim.status_str(rc), "seconds": dt,
+                            "solves_per_s": len(probs) / dt, "max_rel_residual": float(res.max()),
+                            "sweeps": its.tolist()}
+    log(f"[bench] spectral wave: batched mixed solve {dt:.1f} s")
+    t0 = time.perf_counter()
+    bt = thiim.Batch(probs)
+    res = np.full(len(probs), np.inf)
+    while time.perf_counter() - t0 < dt and res.max() > tol:
+        rc, its64, res = bt.solve(tol, 5000, 500)
+        log(f"[bench] spectral wave: FP64 {int((res <= tol).sum())}/{len(probs)} solved, "
+            f"{time.perf_counter() - t0:.1f} s")
+    bt.synchronize()
+    dt64 = time.perf_counter() - t0
+    bt.close()
+    torch.cuda.empty_cache()
+    done = int((res <= tol).sum())
+    out["batched_fp64_same_time"] = {"seconds": dt64, "solved": done,
+                                     "max_rel_residual": float(res.max())}
+    return out
+
+
 def traffic_for(kernel_name, n_cells):
     """Counter traffic (bytes per launch) if the committed summary matches
     the current kernel sources and grid, else None."""
@@ -591,9 +648,10 @@ def main():
         solve = solve_512_context(torch, thiim, dev, n)
         nx_, ny_, nz_ = (int(v) for v in args.solve_grid.split("x"))
         solve_small = solve_context(torch, thiim, inputs, (nz_, ny_, nx_))
-    spectral = None
+    spectral = wave = None
     if not args.no_spectral:
         spectral = spectral_context(torch, thiim, inputs)
+        wave = spectral_wave_context(torch, thiim, inputs)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
@@ -643,6 +701,7 @@ def main():
         "solve_1e-8": solve,
         "solve_1e-8_small": solve_small,
         "spectral_batch": spectral,
+        "spectral_wave": wave,
     }
     print(json.dumps(out), flush=True)
 

@@ -219,9 +219,16 @@ typedef struct {
     int tile_x, tile_y;       /* fused tile or blocked region */
     int t_block;              /* iterations per pass (1 fused, 2 blocked) */
     int z_chunk;              /* planes per workgroup stream */
-    double ms_per_iteration;  /* measured */
+    double ms_per_iteration;  /* measured (of the configuration applied) */
     double model_ms;          /* modelled (see below) */
     int candidates, timed;    /* configurations considered / timed */
+    /* thiim_batch_autotune: time per iteration of the batch with the best
+     * single configuration for all problems (the one described above) and
+     * with each grid's own thiim_autotune choice; per_grid = 1 when the
+     * latter was faster and applied.  thiim_autotune: one_for_all_ms = the
+     * measured time, per_grid_ms = 0, per_grid = 0. */
+    double one_for_all_ms, per_grid_ms;
+    int per_grid;
 } thiim_tuning;
 
 /* Picks the sweep configuration of thiim_iterate for this context: every
@@ -235,6 +242,14 @@ typedef struct {
  * is kept.  All configurations give bit-identical iterates.
  * out may be NULL.  Synchronising. */
 int thiim_autotune(thiim_ctx *ctx, int trial_iters, thiim_tuning *out);
+
+/* Applies a sweep configuration chosen earlier (by thiim_autotune on a
+ * context of the same grid, e.g. one kept in a tuner cache keyed by grid,
+ * storage, precision and device) without timing anything: kernel FUSED or
+ * BLOCKED, a tile / region that thiim_autotune can choose, 1 <= z_chunk <=
+ * nz; the other fields are ignored.  All configurations give bit-identical
+ * iterates.  THIIM_EINVAL on anything else (the context is unchanged). */
+int thiim_apply_tuning(thiim_ctx *ctx, const thiim_tuning *tuning);
 
 /* ---- batches ------------------------------------------------------------ */
 
@@ -291,14 +306,16 @@ int thiim_batch_residual(thiim_batch *batch, double *rel_res);
 int thiim_batch_solve(thiim_batch *batch, double tol, int max_it, int check_every,
                       int *iters, double *rel_res);
 
-/* Picks one sweep configuration for every context of the batch by timing
- * the batched passes themselves (blocked regions 32x16, 64x8, 64x6 and fused
- * tiles 64x8, 32x8, with each problem's automatic z chunk or a fixed one;
- * trial passes from the current states into the spare buffers, so the
- * states do not advance).  In a batch the launch is filled by all problems
- * together, so the choice can differ from thiim_autotune's on each problem
- * alone.  z_chunk = 0 in out means "each problem's automatic chunk".
- * out may be NULL.  Synchronising. */
+/* Picks the sweep configurations of the batch by timing the batched passes
+ * themselves (trial passes from the current states into the spare buffers,
+ * so the states do not advance), two ways, and keeps the faster: one
+ * configuration for every problem (blocked regions 32x16, 64x8, 64x6 and
+ * fused tiles 64x8, 32x8, with each problem's automatic z chunk or a fixed
+ * one), and per grid shape the choice of thiim_autotune on one problem of
+ * that shape alone.  In a batch the launch is filled by all problems
+ * together, so the two can differ.  out describes the best single
+ * configuration (z_chunk = 0: each problem's automatic chunk) and both
+ * timings.  out may be NULL.  Synchronising. */
 int thiim_batch_autotune(thiim_batch *batch, int trial_iters, thiim_tuning *out);
 
 void thiim_batch_destroy(thiim_batch *batch);

@@ -941,7 +941,27 @@ int thiim_autotune(thiim_ctx* c, int trial_iters, thiim_tuning* out) {
         out->model_ms = keep[best].model_ms;
         out->candidates = (int)all.size();
         out->timed = (int)keep.size();
+        out->one_for_all_ms = best_ms;
+        out->per_grid_ms = 0.0;
+        out->per_grid = 0;
     }
+    return THIIM_OK;
+}
+
+int thiim_apply_tuning(thiim_ctx* c, const thiim_tuning* t) {
+    if (!c || !t) return fail(THIIM_EINVAL, "ctx / tuning is NULL");
+    const bool blocked = t->kernel == THIIM_KERNEL_BLOCKED;
+    if (!blocked && t->kernel != THIIM_KERNEL_FUSED)
+        return fail(THIIM_EINVAL, "apply_tuning: kernel must be FUSED or BLOCKED");
+    const bool ok = blocked ? ((t->tile_x == 32 && t->tile_y == 16) ||
+                               (t->tile_x == 64 && (t->tile_y == 8 || t->tile_y == 6)))
+                            : ((t->tile_x == 64 && (t->tile_y == 8 || t->tile_y == 4)) ||
+                               (t->tile_x == 32 && t->tile_y == 8) ||
+                               (t->tile_x == 16 && t->tile_y == 16));
+    if (!ok) return fail(THIIM_EINVAL, "apply_tuning: tile / region not supported");
+    if (t->z_chunk < 1 || t->z_chunk > c->g.nz)
+        return fail(THIIM_EINVAL, "apply_tuning: z_chunk must be in [1, nz]");
+    apply(c, Candidate{t->kernel, t->tile_x, t->tile_y, t->z_chunk, 0.0});
     return THIIM_OK;
 }
 
@@ -1264,7 +1284,8 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                         it.window = Kp[i];
                         it.g = c->geo;
                         it.kchunk = c->inner_chunk;
-                        const int ox = c->inner_rx - 2 * gr.T, oy = c->inner_ry - 2 * gr.T;
+                        const int ox = 32 - 2 * gr.T;
+                        const int oy = thiim::batch_inner_ry(gr.T) - 2 * gr.T;
                         it.ntx = (c->g.nx + ox - 1) / ox;
                         it.nty = (c->g.ny + oy - 1) / oy;
                         it.ntz = (c->g.nz + it.kchunk - 1) / it.kchunk;
@@ -1569,61 +1590,99 @@ int thiim_batch_autotune(thiim_batch* b, int trial_iters, thiim_tuning* out) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(THIIM_EDEVICE, "batch autotune: event create");
+    // Time of one iteration of every problem under the current assignment:
+    // rounds of two iterations each (one pass of each blocked group, two of
+    // each fused group), from the current states into the spare buffers (the
+    // states do not advance).
+    auto time_current = [&](double* per_it) {
+        int rc2 = rebuild(b);
+        if (rc2) return rc2;
+        auto round = [&]() {
+            hipError_t e = hipSuccess;
+            for (auto& gr : b->groups) {
+                for (int rep = 0; rep < (gr.blocked ? 1 : 2) && e == hipSuccess; ++rep)
+                    e = gr.blocked
+                            ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                          gr.total, 2, gr.tx, gr.ty, b->queue,
+                                                          b->ncu, b->stream)
+                            : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
+                                                        gr.total, gr.tx, gr.ty, b->queue,
+                                                        b->ncu, b->stream);
+            }
+            return e;
+        };
+        const int rounds = (trial_iters + 1) / 2;
+        hipError_t e = round();
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int p = 0; e == hipSuccess && p < rounds; ++p) e = round();
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) return hip_fail(e, "batch autotune trial");
+        *per_it = ms / (2.0 * rounds);
+        return THIIM_OK;
+    };
+    // one configuration for every problem
     int best = -1;
     double best_ms = INFINITY;
     int rc = THIIM_OK;
     for (size_t i = 0; i < cands.size() && rc == THIIM_OK; ++i) {
         apply_all(cands[i]);
-        rc = rebuild(b);
-        if (rc) break;
-        const int per = cands[i].kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
-        const int passes = (trial_iters + per - 1) / per;
-        // passes from the current states into the spare buffers (no advance)
-        auto launch_all = [&]() {
-            hipError_t e = hipSuccess;
-            for (auto& gr : b->groups) {
-                if (e != hipSuccess) break;
-                e = gr.blocked ? thiim::launch_blocked_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                             gr.total, 2, gr.tx, gr.ty, b->queue,
-                                                             b->ncu, b->stream)
-                               : thiim::launch_fused_batch(gr.dev[gr.par], (int)gr.members.size(),
-                                                           gr.total, gr.tx, gr.ty, b->queue,
-                                                           b->ncu, b->stream);
-            }
-            return e;
-        };
-        hipError_t e = launch_all();
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        for (int p = 0; e == hipSuccess && p < passes; ++p) e = launch_all();
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "batch autotune trial");
-            break;
-        }
-        const double per_it = ms / (passes * per);
-        if (per_it < best_ms) {
+        double per_it = INFINITY;
+        rc = time_current(&per_it);
+        if (rc == THIIM_OK && per_it < best_ms) {
             best_ms = per_it;
             best = (int)i;
         }
+    }
+    // per grid: each distinct grid shape takes the choice of thiim_autotune on
+    // one of its problems alone, then the batch is timed with that mix
+    double grid_ms = INFINITY;
+    std::vector<Candidate> grid_cfg(b->ctx.size());
+    for (size_t i = 0; i < b->ctx.size() && rc == THIIM_OK; ++i) {
+        const thiim_grid& gi = b->ctx[i]->g;
+        size_t j = 0;
+        while (j < i && !(b->ctx[j]->g.nx == gi.nx && b->ctx[j]->g.ny == gi.ny &&
+                          b->ctx[j]->g.nz == gi.nz))
+            ++j;
+        if (j < i) {
+            grid_cfg[i] = grid_cfg[j];
+            continue;
+        }
+        thiim_tuning t;
+        rc = thiim_autotune(b->ctx[i], trial_iters, &t);
+        grid_cfg[i] = Candidate{t.kernel, t.tile_x, t.tile_y, t.z_chunk, 0.0};
+    }
+    if (rc == THIIM_OK) {
+        for (size_t i = 0; i < b->ctx.size(); ++i) apply(b->ctx[i], grid_cfg[i]);
+        b->dirty = true;
+        rc = time_current(&grid_ms);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (best < 0) return fail(THIIM_EDEVICE, "batch autotune: no trial produced a timing");
-    apply_all(cands[best]);
+    const bool per_grid = grid_ms < best_ms;
+    if (per_grid) {
+        for (size_t i = 0; i < b->ctx.size(); ++i) apply(b->ctx[i], grid_cfg[i]);
+        b->dirty = true;
+    } else {
+        apply_all(cands[best]);
+    }
     if (out) {
         out->kernel = cands[best].kernel;
         out->tile_x = cands[best].tx;
         out->tile_y = cands[best].ty;
         out->t_block = cands[best].kernel == THIIM_KERNEL_BLOCKED ? 2 : 1;
         out->z_chunk = cands[best].chunk;
-        out->ms_per_iteration = best_ms;
+        out->ms_per_iteration = per_grid ? grid_ms : best_ms;
         out->model_ms = 0.0;
-        out->candidates = (int)cands.size();
-        out->timed = (int)cands.size();
+        out->candidates = (int)cands.size() + 1;
+        out->timed = (int)cands.size() + 1;
+        out->one_for_all_ms = best_ms;
+        out->per_grid_ms = grid_ms;
+        out->per_grid = per_grid ? 1 : 0;
     }
     return THIIM_OK;
 }

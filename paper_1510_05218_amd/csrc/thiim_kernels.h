@@ -138,6 +138,9 @@ hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int
                               int tile_y, unsigned int* queue, int ncu, hipStream_t s);
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,
                                 int ry, unsigned int* queue, int ncu, hipStream_t s);
+// Regions of the batched inner passes: 32 x 24 for two sweeps per pass,
+// 32 x 16 for three.
+constexpr int batch_inner_ry(int T) { return T == 2 ? 24 : 16; }
 // left: passes of the step after this one (an item sums its last `window`);
 // max_window: the largest window of the items
 hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total, int T, int left,

@@ -1545,7 +1545,8 @@ __global__ __launch_bounds__(TX* TY) void k_fused_batch(const BatchItem* __restr
 }
 
 template <int RX, int RY, int T, class P>
-__global__ __launch_bounds__(RX* RY, (P::MIN_WAVES > 0 ? P::MIN_WAVES : 1)) void k_inner32_batch(
+__global__ __launch_bounds__(RX* RY, (P::MIN_WAVES > 0 ? (RX * RY > 768 ? 4 : 3) : 1)) void
+k_inner32_batch(
     const BatchItem32* __restrict__ items, int nitems, int total, int left,
     unsigned int* __restrict__ queue) {
     run_queue(queue, total, [&](int t) {
@@ -2580,12 +2581,14 @@ hipError_t launch_inner32_batch(const BatchItem32* items, int nitems, int total,
                                 int max_window, unsigned int* queue, int ncu, hipStream_t s) {
     if (nitems < 1 || total < 1 || !queue) return hipErrorInvalidValue;
     const bool acc = left < max_window;  // some item sums this pass
-    // two-sweep passes read the items' r_T (last-stage source)
+    // two-sweep passes read the items' r_T (last-stage source); regions of
+    // 32 x 24 at three waves per SIMD (the queue loop and the item lookup do
+    // not fit the 128 VGPRs of 32 x 32 regions at four)
     if (T == 2 && acc)
-        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32LA>>(1024, items, nitems, total,
+        return launch_queued_pass<k_inner32_batch<32, 24, 2, Pol32LA>>(768, items, nitems, total,
                                                                         left, queue, ncu, s);
     if (T == 2)
-        return launch_queued_pass<k_inner32_batch<32, 32, 2, Pol32L>>(1024, items, nitems, total,
+        return launch_queued_pass<k_inner32_batch<32, 24, 2, Pol32L>>(768, items, nitems, total,
                                                                        left, queue, ncu, s);
     if (T == 3 && acc)
         return launch_queued_pass<k_inner32_batch<32, 16, 3, Pol32A>>(512, items, nitems, total,

@@ -34,7 +34,7 @@ SYMBOLS = ("thiim_workspace_bytes", "thiim_create", "thiim_iterate",
            "thiim_adjoint_grad", "thiim_autotune", "thiim_batch_workspace_bytes",
            "thiim_batch_create", "thiim_batch_iterate", "thiim_batch_residual",
            "thiim_batch_solve", "thiim_batch_autotune", "thiim_batch_destroy",
-           "thiim_batch_create_static", "thiim_stream_probe",
+           "thiim_batch_create_static", "thiim_stream_probe", "thiim_apply_tuning",
            "thiim_destroy",
            "thiim_last_error", "thiim_status_str")
 
@@ -60,7 +60,9 @@ class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
                 ("t_block", ctypes.c_int), ("z_chunk", ctypes.c_int),
                 ("ms_per_iteration", ctypes.c_double), ("model_ms", ctypes.c_double),
-                ("candidates", ctypes.c_int), ("timed", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("timed", ctypes.c_int),
+                ("one_for_all_ms", ctypes.c_double), ("per_grid_ms", ctypes.c_double),
+                ("per_grid", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,6 +100,7 @@ def lib():
         L.thiim_iterations.argtypes = [vp, P(ctypes.c_longlong)]
         L.thiim_adjoint_grad.argtypes = [vp, vp, d, i, i, vp, P(d), P(i), P(d)]
         L.thiim_autotune.argtypes = [vp, i, P(Tuning)]
+        L.thiim_apply_tuning.argtypes = [vp, P(Tuning)]
         L.thiim_batch_workspace_bytes.argtypes = [i, P(ctypes.c_size_t)]
         L.thiim_batch_create.argtypes = [P(vp), i, vp, ctypes.c_size_t, P(vp)]
         L.thiim_batch_create_static.argtypes = [P(vp), i, P(vp)]
@@ -204,6 +207,54 @@ def thiim_autotune(ctx, trial_iters: int = 10) -> Tuning:
     out = Tuning()
     _check(lib().thiim_autotune(ctx, int(trial_iters), ctypes.byref(out)))
     return out
+
+
+def thiim_apply_tuning(ctx, tuning: dict):
+    t = Tuning(**{k: tuning[k] for k, _ in Tuning._fields_ if k in tuning})
+    _check(lib().thiim_apply_tuning(ctx, ctypes.byref(t)))
+
+
+class TunerCache:
+    """Persisted thiim_autotune choices, a JSON file keyed by what decides the
+    choice: grid shape, boundaries, storage, precision and the device (name,
+    architecture, compute units).  ``Solver.autotune(cache=...)`` applies a
+    cached entry (thiim_apply_tuning) instead of timing, and stores what it
+    times.  Writes go to a temporary file that replaces the old one."""
+
+    def __init__(self, path):
+        import json
+
+        self.path = path
+        self.entries = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                self.entries = json.load(f)
+
+    @staticmethod
+    def key(grid: Grid, device: str) -> str:
+        return (f"{grid.nx}x{grid.ny}x{grid.nz}|bc{grid.bc_x}{grid.bc_y}|s{grid.storage}"
+                f"|p{grid.precision}|{device}")
+
+    def get(self, key):
+        return self.entries.get(key)
+
+    def put(self, key, tuning: dict):
+        import json
+
+        self.entries[key] = {k: tuning[k] for k in ("kernel", "tile_x", "tile_y", "t_block",
+                                                    "z_chunk", "ms_per_iteration")}
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def device_key(device) -> str:
+    """Name, architecture and compute units of a torch device."""
+    import torch
+
+    p = torch.cuda.get_device_properties(device)
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}cu"
 
 
 def thiim_batch_workspace_bytes(n: int) -> int:
@@ -346,9 +397,22 @@ class Solver:
         inner sweeps per correction, 0 = adaptive."""
         return thiim_solve(self.ctx, tol, max_it, check_every)
 
-    def autotune(self, trial_iters=10):
-        """Chooses this context's sweep configuration (thiim_autotune)."""
-        return thiim_autotune(self.ctx, trial_iters).as_dict()
+    def autotune(self, trial_iters=10, cache=None):
+        """Chooses this context's sweep configuration (thiim_autotune).  With
+        a :class:`TunerCache`, a configuration cached for the same grid,
+        storage, precision and device is applied without timing (the result
+        then carries ``"cached": True``); otherwise the timed choice is
+        stored in the cache."""
+        if cache is not None:
+            key = TunerCache.key(self.grid, device_key(self.device))
+            hit = cache.get(key)
+            if hit is not None:
+                thiim_apply_tuning(self.ctx, hit)
+                return {**hit, "cached": True}
+        out = thiim_autotune(self.ctx, trial_iters).as_dict()
+        if cache is not None:
+            cache.put(key, out)
+        return out
 
     def _lib_stream(self):
         """Context for torch work whose results the library reads or writes:

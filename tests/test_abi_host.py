@@ -109,3 +109,27 @@ def test_missing_library_fails_loudly():
                        text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     assert "raised:" in r.stdout and "no CPU fallback" in r.stdout
+
+
+def test_tuner_cache_round_trip(tmp_path):
+    """The tuner cache persists entries keyed by grid, boundaries, storage,
+    precision and device, and survives a reload."""
+    path = str(tmp_path / "tune.json")
+    g = thiim.make_grid((36, 24, 24), storage="compact")
+    g2 = thiim.make_grid((36, 24, 24), storage="full")
+    c = thiim.TunerCache(path)
+    k = thiim.TunerCache.key(g, "dev")
+    assert c.get(k) is None
+    c.put(k, {"kernel": 3, "tile_x": 32, "tile_y": 16, "t_block": 2, "z_chunk": 36,
+              "ms_per_iteration": 0.1, "model_ms": 0.0})
+    c2 = thiim.TunerCache(path)
+    assert c2.get(k)["tile_y"] == 16 and "model_ms" not in c2.get(k)
+    assert c2.get(thiim.TunerCache.key(g2, "dev")) is None
+    assert c2.get(thiim.TunerCache.key(g, "other device")) is None
+
+
+def test_apply_tuning_rejects_null():
+    with pytest.raises(thiim.ThiimError) as e:
+        thiim.thiim_apply_tuning(None, {"kernel": 3, "tile_x": 32, "tile_y": 16,
+                                        "z_chunk": 4})
+    assert e.value.status == thiim.THIIM_EINVAL

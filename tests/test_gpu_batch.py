@@ -178,7 +178,11 @@ def test_batch_autotune_keeps_iterates():
     probs = [inputs.random_problem(40, 36, 20, seed=91), inputs.random_problem(70, 20, 30, seed=92)]
     bt = thiim.Batch(probs, autotune=True, trial_iters=4)
     t = bt.tuning
-    assert t["kernel"] in (thiim.KERNELS["fused"], thiim.KERNELS["blocked"]) and t["timed"] == 13
+    assert t["kernel"] in (thiim.KERNELS["fused"], thiim.KERNELS["blocked"]) and t["timed"] == 14
+    # both ways were timed and the faster applied
+    assert t["one_for_all_ms"] > 0 and t["per_grid_ms"] > 0
+    assert t["ms_per_iteration"] == min(t["one_for_all_ms"], t["per_grid_ms"])
+    assert t["per_grid"] == int(t["per_grid_ms"] < t["one_for_all_ms"])
     bt.iterate(70)
     bt.synchronize()
     for s, pb in zip(bt.solvers, probs):

@@ -67,3 +67,32 @@ def test_autotune_on_thin_grids(nz):
     assert torch.equal(s.fields(), xr)
     ref.close()
     s.close()
+
+
+def test_tuner_cache_applies_without_timing(tmp_path):
+    """The first autotune on a grid times and stores its choice; a second
+    context of the same grid takes it from the cache (no timing) and
+    iterates bit-identically; invalid configurations are rejected."""
+    _require_gpu()
+    print("[guards] tuner cache", flush=True)
+    pb = inputs.random_problem(40, 30, 24, seed=79)
+    cache = thiim.TunerCache(str(tmp_path / "tune.json"))
+    s1 = thiim.Solver(pb, storage="compact")
+    t1 = s1.autotune(3, cache=cache)
+    assert not t1.get("cached") and t1["timed"] >= 1
+    s2 = thiim.Solver(pb, storage="compact")
+    t2 = s2.autotune(3, cache=thiim.TunerCache(str(tmp_path / "tune.json")))
+    assert t2["cached"] and (t2["kernel"], t2["tile_x"], t2["tile_y"], t2["z_chunk"]) == \
+        (t1["kernel"], t1["tile_x"], t1["tile_y"], t1["z_chunk"])
+    ref = thiim.Solver(pb, kernel="naive", storage="compact")
+    for s in (s1, s2, ref):
+        s.iterate(11)
+    assert torch.equal(s2.fields(), ref.fields()) and torch.equal(s1.fields(), ref.fields())
+    for bad in ({"kernel": 1, "tile_x": 64, "tile_y": 8, "z_chunk": 4},
+                {"kernel": 3, "tile_x": 48, "tile_y": 8, "z_chunk": 4},
+                {"kernel": 2, "tile_x": 64, "tile_y": 8, "z_chunk": 0}):
+        with pytest.raises(thiim.ThiimError) as e:
+            thiim.thiim_apply_tuning(s2.ctx, bad)
+        assert e.value.status == thiim.THIIM_EINVAL
+    for s in (s1, s2, ref):
+        s.close()
