@@ -2,6 +2,8 @@
 
 * ``kernel_stats_md``: the ``--kernel-trace --stats`` CSV as a markdown table
   with achieved algorithmic bandwidth per kernel.
+* ``counters_md``: occupancy, wait shares and instruction mix per kernel from
+  ``--pmc`` runs of SQ counters and MeanOccupancyPerCU.
 * ``traffic_summary``: per-dispatch ``FETCH_SIZE`` / ``WRITE_SIZE`` (KiB) from
   two ``--pmc`` runs, each scaled by what the same counter reads for a plain
   device copy of known size run in the same process (the calibration copy of
@@ -24,6 +26,7 @@
 Usage:
     python -m paper_1510_05218_amd.profiling traffic FETCH.csv WRITE.csv N OUT.json CMD [FS WS]
     python -m paper_1510_05218_amd.profiling stats STATS.csv N OUT.md CMD [NAME,NAME...]
+    python -m paper_1510_05218_amd.profiling counters SQ.csv OCC.csv OUT.md CMD [NAME,...]
     python -m paper_1510_05218_amd.profiling run_kernels [n]
     python -m paper_1510_05218_amd.profiling run_mixed [n]
     python -m paper_1510_05218_amd.profiling run_solve [n]
@@ -74,7 +77,17 @@ ALG_BYTES_PER_CELL = {
     # at 512^3 with 6-plane PMLs (13 H and 12 E planes not symmetric)
     "k_blocked<32,16,3,Pol32>": 162,
     "k_blocked<32,32,2,Pol32R>": 162,
-    "k_inner32_batch<32,32,2,Pol32R>": 162,
+    # two-sweep passes with the pass source r_T = (I + M) r read once, at the
+    # last stage (the same algorithmic bytes)
+    "k_blocked<32,32,2,Pol32L>": 162,
+    "k_inner32_batch<32,24,2,Pol32L>": 162,
+    "k_inner32_batch<32,16,3,Pol32>": 162,
+    # the last Kp passes of a correction also read and write the window sum
+    # (6 complex64 values in pair-sum form): + 96 B
+    "k_blocked<32,32,2,WithAcc<Pol32L>>": 258,
+    "k_blocked<32,16,3,WithAcc<Pol32>>": 258,
+    "k_inner32_batch<32,24,2,WithAcc<Pol32L>>": 258,
+    "k_inner32_batch<32,16,3,WithAcc<Pol32>>": 258,
 }
 
 
@@ -89,6 +102,47 @@ def code_balance(rx, ry, t, b_read, b_write, nx, ny):
     tiles_x, tiles_y = -(-nx // ox), -(-ny // oy)
     read_per_cell = b_read * tiles_x * tiles_y * rx * ry / (nx * ny)
     return (read_per_cell + b_write) / t
+
+
+# The temporally blocked sweeps of the measured bytes-per-update table: name,
+# storage / precision, iterations per pass T, region (rx, ry), bytes read per
+# region column and pass (b_read), bytes written per stored column (b_write)
+# -- the GPU form of the paper's code-balance model, Eq. 12 -- with T = 1 the
+# fused single-iteration sweep (its halo is a one-column ring of E sums).
+BALANCE_CASES = [
+    ("k_fused<64,8,CompactCoefs>", "FP64 compact", 1, None, 208, 192),
+    ("k_blocked<32,16,2,Pol64<CompactCoefs>>", "FP64 compact", 2, (32, 16), 208, 192),
+    ("k_fused<64,8,FullCoefs>", "FP64 40-array", 1, None, 576, 192),
+    # each stage reads its planes' 24 t/c arrays: 12 fields + 2 x 24 t/c
+    ("k_blocked<64,8,2,Pol64<FullCoefs>>", "FP64 40-array", 2, (64, 8), 960, 192),
+    # complex64 pair-sum form off the PML: d 48 + source 48 + record 16 read,
+    # d 48 written; the two-sweep form reads the record at both stages (+16)
+    ("k_blocked<32,32,2,Pol32L>", "complex64 inner", 2, (32, 32), 128, 48),
+    ("k_blocked<32,16,3,Pol32>", "complex64 inner", 3, (32, 16), 112, 48),
+]
+
+
+def balance_table(traffic_json, n=512):
+    """Markdown table: measured counter bytes per lattice update of each
+    sweep in BALANCE_CASES (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch / T /
+    cells, from a traffic summary) against the overlapped-tile code-balance
+    model at n x n planes (T = 1: bytes read + written per cell)."""
+    t = json.load(open(traffic_json))
+    lines = ["| sweep | storage / precision | T | region | model B/LUP | measured B/LUP | "
+             "measured / model |", "|---|---|---|---|---|---|---|"]
+    rows = []
+    for name, what, T, region, br, bw in BALANCE_CASES:
+        k = t["kernels"].get(name)
+        if k is None:
+            continue
+        model = (br + bw) if region is None else code_balance(region[0], region[1], T, br, bw,
+                                                              n, n)
+        meas = k["bytes_per_cell"] / T
+        rows.append((name, what, T, region, model, meas))
+        reg = "-" if region is None else f"{region[0]} x {region[1]}"
+        lines.append(f"| {name} | {what} | {T} | {reg} | {model:.1f} | {meas:.1f} | "
+                     f"{meas / model:.2f} |")
+    return "\n".join(lines) + "\n", rows
 
 
 def source_hash() -> str:
@@ -166,17 +220,63 @@ def kernel_stats_md(stats_csv, n_cells, out_md, command, only=None):
         rows = [r for r in rows if any(k in r["Name"] for k in keys)]
     lines = ["# THIIM kernels: rocprofv3 kernel statistics", "",
              "Command:", "", "```", command, "```", "",
-             f"Grid: {n_cells} cells.  Achieved = algorithmic bytes per launch / average "
-             "duration.", "",
+             (f"Grid: {n_cells} cells.  Achieved = algorithmic bytes per launch / average "
+              "duration." if n_cells > 1 else
+              "Launches over problem sets of different sizes: no bandwidth computed."), "",
              "| kernel | calls | avg (ms) | min (ms) | max (ms) | alg. B/cell | achieved GB/s |",
              "|---|---|---|---|---|---|---|"]
     for r in rows:
         name = short_name(r["Name"])
         avg = float(r["AverageNs"]) / 1e6
         b = ALG_BYTES_PER_CELL.get(name)
-        gbs = f"{b * n_cells / (avg * 1e-3) / 1e9:.0f}" if b else "-"
+        gbs = f"{b * n_cells / (avg * 1e-3) / 1e9:.0f}" if b and n_cells > 1 else "-"
         lines.append(f"| {name} | {r['Calls']} | {avg:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
                      f"{float(r['MaxNs']) / 1e6:.3f} | {b if b else '-'} | {gbs} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def counters_md(sq_csv, occ_csv, out_md, command, only=None):
+    """Per-kernel averages of a ``--pmc`` run of the SQ counters (waves, wave
+    cycles, cycles waiting on memory / on instruction issue, VALU and LDS
+    instructions, LDS bank conflicts) and of one of MeanOccupancyPerCU, as a
+    markdown table: waves resident per CU, the share of wave time spent
+    waiting, VALU instructions per wave, and LDS instructions and bank
+    conflicts per wave."""
+    def load(path):
+        agg = defaultdict(lambda: defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            agg[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    sq, occ = load(sq_csv), load(occ_csv)
+    keys = sorted(k for k in sq if k.startswith("k_"))
+    if only:
+        keys = [k for k in keys if any(o in k for o in only.split(","))]
+    lines = ["# THIIM kernels: occupancy, waits and instruction mix (rocprofv3 --pmc)", "",
+             "Command (one run per counter set):", "", "```", command, "```", "",
+             "Per launch, averaged over launches: occupancy = MeanOccupancyPerCU (waves "
+             "resident per CU, of at most 32); wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES (share "
+             "of wave time waiting on memory or LDS counters); issue = "
+             "SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (waiting for an instruction to issue); "
+             "VALU, LDS = instructions per wave; conflicts = SQ_LDS_BANK_CONFLICT cycles "
+             "per wave.", "",
+             "| kernel | launches | waves | occupancy | wait | issue | VALU/wave | LDS/wave | "
+             "conflicts/wave |", "|---|---|---|---|---|---|---|---|---|"]
+    for k in keys:
+        d = sq[k]
+
+        def g(c, d=d):
+            return sum(d[c]) / len(d[c]) if c in d else float("nan")
+
+        waves = g("SQ_WAVES")
+        o = occ.get(k, {}).get("MeanOccupancyPerCU", [])
+        oc = f"{sum(o) / len(o):.1f}" if o else "-"
+        lines.append(f"| {k} | {len(d['SQ_WAVES'])} | {waves:.0f} | {oc} | "
+                     f"{g('SQ_WAIT_ANY') / g('SQ_WAVE_CYCLES'):.2f} | "
+                     f"{g('SQ_WAIT_INST_ANY') / g('SQ_WAVE_CYCLES'):.2f} | "
+                     f"{g('SQ_INSTS_VALU') / waves:.0f} | {g('SQ_INSTS_LDS') / waves:.0f} | "
+                     f"{g('SQ_LDS_BANK_CONFLICT') / waves:.0f} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -438,6 +538,13 @@ def main(argv):
     elif argv[0] == "stats":
         stats, n, out, cmd = argv[1:5]
         kernel_stats_md(stats, int(n), out, cmd, argv[5] if len(argv) > 5 else None)
+        print(open(out).read())
+    elif argv[0] == "balance":
+        md, _ = balance_table(argv[1])
+        print(md)
+    elif argv[0] == "counters":
+        sq, occ, out, cmd = argv[1:5]
+        counters_md(sq, occ, out, cmd, argv[5] if len(argv) > 5 else None)
         print(open(out).read())
     elif argv[0] == "run_kernels":
         run_kernels(int(argv[1]) if len(argv) > 1 else 512)
