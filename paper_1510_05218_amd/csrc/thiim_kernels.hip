@@ -412,6 +412,9 @@ struct Pol64 {
     static constexpr int MIN_WAVES = 0;  // no occupancy request
     static constexpr bool XL = false;    // neighbour sums through LDS
     static constexpr bool SRC_LAST = false;
+    // compact storage: H_0 of the next plane is read half a step early (on
+    // the 40-array layout the extra 24 registers spill)
+    static constexpr bool PREFETCH_H = CP::COMPACT;
     static constexpr int HMASK = SRC_MASK_Z, EMASK = SRC_MASK_Z;
     static constexpr bool H_SRC_AFTER = false;
     static constexpr bool CARRY = false;
@@ -487,6 +490,7 @@ struct Pol32 {
     static constexpr int MIN_WAVES = 0;
     static constexpr bool XL = false;
     static constexpr bool SRC_LAST = false;
+    static constexpr bool PREFETCH_H = false;
     static constexpr int HMASK = 0, EMASK = SRC_MASK_ALL;
     static constexpr bool H_SRC_AFTER = true;
     // sources and the E-coefficient record are loaded once, by the first
@@ -1217,19 +1221,31 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
         }
     }
     if (ks > 0 && valid) pol.load_e(AE, S, ks - 1, (ks - 1) * plane, bo, e0p);
+    // PREFETCH_H: H_0 of plane k + 1 is read during step k, once stage 1 has
+    // consumed H_0 of plane k, so that it is in flight across stage 2
+    V h0n[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) h0n[q] = vzero<V>();
+    if (P::PREFETCH_H && ks < g.nz && valid) pol.load_h(A, S, ks, ks * plane, bo, h0n);
     __syncthreads();
 
     for (int k = ks; k <= kend; ++k) {
         const int par = k & 1;
         // every HBM read of the step is issued here, before the first barrier,
-        // so that their latencies overlap: E_0 and H_0 of plane k, and the
-        // sources or coefficient record that the policy carries
+        // so that their latencies overlap: E_0 and H_0 of plane k (H_0 already
+        // during the previous step with PREFETCH_H: reads issued after this
+        // step's stores would also wait for those stores to complete, the
+        // vector-memory counter being in order), and the sources or
+        // coefficient record that the policy carries
         V e0c[6], h0c[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) e0c[q] = h0c[q] = vzero<V>();
+        for (int q = 0; q < 6; ++q) {
+            e0c[q] = vzero<V>();
+            h0c[q] = P::PREFETCH_H ? h0n[q] : vzero<V>();
+        }
         if (k < g.nz && valid) {
             pol.load_e(AE, S, k, k * plane, bo, e0c);
-            pol.load_h(A, S, k, k * plane, bo, h0c);
+            if constexpr (!P::PREFETCH_H) pol.load_h(A, S, k, k * plane, bo, h0c);
         }
         if constexpr (P::CARRY) {
 #pragma unroll
@@ -1323,6 +1339,13 @@ __device__ __forceinline__ void blocked_body(const P& pol, const typename P::V* 
                     for (int q = 0; q < 6; ++q) h[q] = cadd(h[q], src[q]);
                 }
                 if (s == T && own && kh >= k0 && kh < k1) pol.store_h(B, S, kh, po, bo, h);
+            }
+            if constexpr (P::PREFETCH_H) {
+                if (s == 1) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h0n[q] = vzero<V>();
+                    if (k + 1 < g.nz && valid) pol.load_h(A, S, k + 1, (k + 1) * plane, bo, h0n);
+                }
             }
             const V hx = hsum[0], hy = hsum[1], hz = hsum[2];
             if constexpr (XL) {
