@@ -41,10 +41,22 @@ constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // (7-8% faster sweeps at 512^3).
 constexpr long long kStridePad = 272;
 
+// Workgroups of one residual-forming fused pass, bounded so that their
+// partial sums fit the workspace: the largest column-tile count of the fused
+// tiles, times 16 z chunks (at least kResidBlocks, the plain reduction's grid).
+int resid_blocks(const thiim_grid* g) {
+    const int tiles[4][2] = {{64, 8}, {32, 8}, {64, 4}, {16, 16}};
+    long long m = 0;
+    for (auto& t : tiles)
+        m = std::max(m, (long long)((g->nx + t[0] - 1) / t[0]) * ((g->ny + t[1] - 1) / t[1]));
+    return (int)std::max<long long>(kResidBlocks, 16 * m);
+}
+
 struct Layout {
     long long N, S;   // cells, array stride (double2)
+    int resid_max;    // workgroups of a residual pass (resid_blocks)
     size_t off_sig;   // 2*nz doubles
-    size_t off_part;  // 2*kResidBlocks doubles
+    size_t off_part;  // 2*resid_max doubles
     size_t off_plane; // nz PlaneCoef
     size_t off_coef;  // full: 28 arrays; compact: eps + 4 Src arrays
     size_t off_a, off_b;
@@ -63,8 +75,9 @@ Layout layout_of(const thiim_grid* g) {
     size_t off = kHeaderBytes;
     L.off_sig = off;
     off = align_up(off + 2 * sizeof(double) * g->nz, kAlign);
+    L.resid_max = resid_blocks(g);
     L.off_part = off;
-    off = align_up(off + 2 * sizeof(double) * kResidBlocks, kAlign);
+    off = align_up(off + 2 * sizeof(double) * L.resid_max, kAlign);
     L.off_plane = off;
     off = align_up(off + sizeof(thiim::PlaneCoef) * g->nz, kAlign);
     L.off_coef = off;
@@ -269,9 +282,22 @@ hipError_t one_pass(thiim_ctx* c, int src, int dst) {
 int reduce_pair(thiim_ctx* c, const double2* A, const double2* B, int c0, double* r2,
                 double* b2);
 
-// r2 = ||P(F[b] - F[a])||^2, b2 = ||P F[b]||^2 (synchronising)
-int reduce(thiim_ctx* c, int a, int b, double* r2, double* b2) {
-    return reduce_pair(c, c->F[a], c->F[b], 0, r2, b2);
+// Phi(F[src]) into F[dst] by the fused pass, with the residual sums of the
+// iteration (||P(F[dst] - F[src])||^2, ||P F[dst]||^2) left in c->out.
+hipError_t residual_pass(thiim_ctx* c, int src, int dst, hipStream_t s) {
+    return thiim::launch_fused_res(c->cv, c->F[src], c->F[dst], c->geo, c->tile_x, c->tile_y,
+                                   c->z_chunk, c->part, c->L.resid_max, c->out, s);
+}
+
+// c->out to the host (synchronising)
+int read_out(thiim_ctx* c, double* r2, double* b2) {
+    double host[2];
+    hipError_t e = hipMemcpyAsync(host, c->out, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual copy");
+    *r2 = host[0];
+    *b2 = host[1];
+    return THIIM_OK;
 }
 
 // r2 = ||P(B - A)||^2, b2 = ||P B||^2 over physical components c0..5
@@ -410,7 +436,9 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     a.flag = c->flag;
     e = thiim::launch_build(a, compact, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "coefficient launch"));
-    e = thiim::launch_fill_zero(c->F[0], 24 * L.S, c->stream);  // both buffers
+    // x = 0; the other buffer needs no clearing: every pass writes all of its
+    // output's cells before anything reads them
+    e = thiim::launch_fill_zero(c->F[0], 12 * L.S, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "zero fields"));
     int flag = 0;
     e = hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -424,10 +452,10 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     }
 
     // ||P Phi(0)||: one iteration from the zero state
-    e = one_pass(c, 0, 1);
+    e = residual_pass(c, 0, 1, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "phi(0) launch"));
     double r2 = 0, b2 = 0;
-    rc = reduce(c, 0, 1, &r2, &b2);
+    rc = read_out(c, &r2, &b2);
     if (rc) return bail(rc);
     c->phi0_norm = std::sqrt(b2);
     if (!std::isfinite(c->phi0_norm)) return bail(fail(THIIM_EINVAL, "non-finite source response"));
@@ -463,10 +491,10 @@ int thiim_iterate(thiim_ctx* c, int n) {
 int thiim_residual(thiim_ctx* c, double* rel_res) {
     if (!c || !rel_res) return fail(THIIM_EINVAL, "ctx / rel_res is NULL");
     const int other = 1 - c->cur;
-    hipError_t e = one_pass(c, c->cur, other);
+    hipError_t e = residual_pass(c, c->cur, other, c->stream);
     if (e != hipSuccess) return hip_fail(e, "residual pass");
     double r2 = 0, b2 = 0;
-    int rc = reduce(c, c->cur, other, &r2, &b2);
+    int rc = read_out(c, &r2, &b2);
     if (rc) return rc;
     const double r = std::sqrt(r2) / (c->phi0_norm > 0 ? c->phi0_norm : 1.0);
     *rel_res = r;
@@ -1160,10 +1188,7 @@ int batch_residual(thiim_batch* b, std::vector<double>& r) {
     for (size_t i = 0; i < n && e == hipSuccess; ++i) {
         if (!b->active[i]) continue;
         thiim_ctx* c = b->ctx[i];
-        e = one_pass(c, c->cur, 1 - c->cur);
-        if (e == hipSuccess)
-            e = thiim::launch_resid(c->F[c->cur], c->F[1 - c->cur], c->L.S, c->L.N, 0, c->part,
-                                    kResidBlocks, c->out, b->stream);
+        e = residual_pass(c, c->cur, 1 - c->cur, b->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&host[2 * i], c->out, 2 * sizeof(double), hipMemcpyDeviceToHost,
                                b->stream);

@@ -106,6 +106,13 @@ hipError_t launch_naive(const CoefView& cv, double2* F, const Geo& g, int kchunk
                         hipStream_t s);
 hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                         int tile_x, int tile_y, int kchunk, hipStream_t s);
+// The fused pass A -> B that also writes r2 = ||P(B - A)||^2 and b2 = ||P B||^2
+// (physical components, FP64) to out[0], out[1]: one partial pair per
+// workgroup in part (at most max_blocks workgroups; the z chunking is
+// coarsened to fit), summed in a fixed order.
+hipError_t launch_fused_res(const CoefView& cv, const double2* A, double2* B, const Geo& g,
+                            int tile_x, int tile_y, int kchunk, double* part, int max_blocks,
+                            double* out, hipStream_t s);
 hipError_t launch_blocked(const CoefView& cv, const double2* A, double2* B, const Geo& g,
                           int T, int rx, int ry, int kchunk, hipStream_t s);
 // Mixed precision: the per-cell complex64 E-coefficient records and the

@@ -845,6 +845,21 @@ __global__ __launch_bounds__(256) void k_naive_e(CP cp, double2* __restrict__ F,
     }
 }
 
+// Sum of one value per thread over the workgroup (blockDim.x a power of two,
+// sh holding blockDim.x doubles), in a fixed order.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Fused H+E pass, A -> B (one HBM pass per iteration).
 //
@@ -860,11 +875,16 @@ __global__ __launch_bounds__(256) void k_naive_e(CP cp, double2* __restrict__ F,
 // data): its old E parts, its z-neighbour sums and its H sums of the previous
 // plane stay in registers.  A chunk [k0, k1) of planes recomputes H(k1) (not
 // stored) so that chunks are independent.
+//
+// RES: the pass also forms the residual of the iteration, ||P(B - A)||^2 and
+// ||P B||^2 (P the sum of each split pair) over the cells the workgroup
+// stores, from the old and new values it holds in registers, and writes the
+// two workgroup sums to part[2 b], part[2 b + 1] (b the workgroup index).
 // ---------------------------------------------------------------------------
-template <int TX, int TY, class CP>
+template <int TX, int TY, bool RES = false, class CP>
 __device__ __forceinline__ void fused_body(const CP& cp, const double2* __restrict__ A,
                                            double2* __restrict__ B, const Geo& g, int kchunk,
-                                           const Tile T) {
+                                           const Tile T, double* __restrict__ part = nullptr) {
     constexpr int NT = TX * TY;
     constexpr int EW = TX + 2, EH = TY + 2;  // E region [-1,TX] x [-1,TY]
     constexpr int HW = TX + 1, HH = TY + 1;  // H region [0,TX] x [0,TY]
@@ -907,6 +927,19 @@ __device__ __forceinline__ void fused_body(const CP& cp, const double2* __restri
 
     const double2* AE = A + 6 * S;
     double2* BE = B + 6 * S;
+    double r2 = 0.0, b2 = 0.0;  // RES: this thread's sums
+    // RES: the three physical components of new parts v against old parts o
+    auto add_res = [&](const double2 v[6], const double2 o[6]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 d = cadd(csub(v[2 * c], o[2 * c]), csub(v[2 * c + 1], o[2 * c + 1]));
+            const double2 pb = cadd(v[2 * c], v[2 * c + 1]);
+            r2 = __fma_rn(d.x, d.x, r2);
+            r2 = __fma_rn(d.y, d.y, r2);
+            b2 = __fma_rn(pb.x, pb.x, b2);
+            b2 = __fma_rn(pb.y, pb.y, b2);
+        }
+    };
 
     // state carried along z
     double2 eprev[6];  // own E^n parts of plane k-1
@@ -968,9 +1001,17 @@ __device__ __forceinline__ void fused_body(const CP& cp, const double2* __restri
                 nb.ez_xm = Es[2][eo - 1];
                 double2 h[6], t[6], c[6], sa, sb;
                 load6(A, S, po, bo, h);
+                double2 hold[6];
+                if constexpr (RES) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) hold[q] = h[q];
+                }
                 cp.h(k, po, bo, t, c, sa, sb);
                 update_h(h, t, c, sa, sb, nb);
-                if (own_store && k < k1) store6(B, S, po, bo, h);
+                if (own_store && k < k1) {
+                    store6(B, S, po, bo, h);
+                    if constexpr (RES) add_res(h, hold);
+                }
                 hx = cadd(h[0], h[1]);
                 hy = cadd(h[2], h[3]);
                 hz = cadd(h[4], h[5]);
@@ -1009,9 +1050,17 @@ __device__ __forceinline__ void fused_body(const CP& cp, const double2* __restri
             nb.hz_xp = Hs[2][ho + 1];
             const long long pm = po - plane;
             double2 t[6], c[6], sa, sb;
+            double2 eold[6];
+            if constexpr (RES) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) eold[q] = eprev[q];
+            }
             cp.e(k - 1, pm, bo, t, c, sa, sb);
             update_e(eprev, t, c, sa, sb, nb);
-            if (own_store) store6(BE, S, pm, bo, eprev);
+            if (own_store) {
+                store6(BE, S, pm, bo, eprev);
+                if constexpr (RES) add_res(eprev, eold);
+            }
         }
         __syncthreads();
         // ---- phase 4: H sums of plane k into LDS, shift the z state
@@ -1031,6 +1080,17 @@ __device__ __forceinline__ void fused_body(const CP& cp, const double2* __restri
 #pragma unroll
         for (int q = 0; q < 6; ++q) eprev[q] = ecur[q];
     }
+    if constexpr (RES) {
+        static_assert(NT * sizeof(double) <= sizeof(Es), "reduction scratch");
+        double* sh = reinterpret_cast<double*>(&Es[0][0]);
+        __syncthreads();  // the last step's LDS reads are done
+        const double s1 = block_sum(r2, sh);
+        const double s2 = block_sum(b2, sh);
+        if (tid == 0) {
+            part[2 * blockIdx.x] = s1;
+            part[2 * blockIdx.x + 1] = s2;
+        }
+    }
 }
 
 template <int TX, int TY, class CP>
@@ -1040,6 +1100,17 @@ __global__ __launch_bounds__(TX* TY) void k_fused(CP cp, const double2* __restri
     fused_body<TX, TY>(cp, A, B, g, kchunk,
                        tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
                                (g.nz + kchunk - 1) / kchunk));
+}
+
+// The fused pass that also forms the residual sums of the iteration.
+template <int TX, int TY, class CP>
+__global__ __launch_bounds__(TX* TY) void k_fused_res(CP cp, const double2* __restrict__ A,
+                                                      double2* __restrict__ B, Geo g, int kchunk,
+                                                      double* __restrict__ part) {
+    fused_body<TX, TY, true>(cp, A, B, g, kchunk,
+                             tile_of((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY,
+                                     (g.nz + kchunk - 1) / kchunk),
+                             part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1607,18 +1678,6 @@ __global__ __launch_bounds__(RX* RY) void k_blocked_batch(const BatchItem* __res
 // physical components (P: sum of each split pair).  Block partial sums, then
 // one block reduces the partials in a fixed order: deterministic FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
 
 // Physical components c0..5 (0: all, 3: E only) of A and B.
 __global__ __launch_bounds__(256) void k_resid_partial(const double2* __restrict__ A,
@@ -2526,6 +2585,50 @@ hipError_t launch_fused(const CoefView& cv, const double2* A, double2* B, const 
                         int tile_x, int tile_y, int kchunk, hipStream_t s) {
     return cv.compact ? fused_impl(compact_of(cv), A, B, g, tile_x, tile_y, kchunk, s)
                       : fused_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, s);
+}
+
+template <class CP>
+static hipError_t fused_res_impl(const CP& cp, const double2* A, double2* B, const Geo& g,
+                                 int tile_x, int tile_y, int kchunk, double* part, int max_blocks,
+                                 double* out, hipStream_t s) {
+    const long long tiles =
+        (long long)((g.nx + tile_x - 1) / tile_x) * ((g.ny + tile_y - 1) / tile_y);
+    if (tiles > max_blocks) return hipErrorInvalidValue;
+    // the z chunking only changes which workgroup updates a plane, never the
+    // values: take the context's, coarsened until one partial per workgroup fits
+    if (tiles * nchunks(g, kchunk) > max_blocks) {
+        const int per = (int)(max_blocks / tiles);
+        kchunk = (g.nz + per - 1) / per;
+    }
+    const int nblk = (int)(tiles * nchunks(g, kchunk));
+    dim3 grid(nblk);
+    if (tile_x == 64 && tile_y == 8)
+        hipLaunchKernelGGL((k_fused_res<64, 8, CP>), grid, dim3(512), 0, s, cp, A, B, g, kchunk,
+                           part);
+    else if (tile_x == 32 && tile_y == 8)
+        hipLaunchKernelGGL((k_fused_res<32, 8, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk,
+                           part);
+    else if (tile_x == 64 && tile_y == 4)
+        hipLaunchKernelGGL((k_fused_res<64, 4, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk,
+                           part);
+    else if (tile_x == 16 && tile_y == 16)
+        hipLaunchKernelGGL((k_fused_res<16, 16, CP>), grid, dim3(256), 0, s, cp, A, B, g, kchunk,
+                           part);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_res(const CoefView& cv, const double2* A, double2* B, const Geo& g,
+                            int tile_x, int tile_y, int kchunk, double* part, int max_blocks,
+                            double* out, hipStream_t s) {
+    return cv.compact ? fused_res_impl(compact_of(cv), A, B, g, tile_x, tile_y, kchunk, part,
+                                       max_blocks, out, s)
+                      : fused_res_impl(full_of(cv), A, B, g, tile_x, tile_y, kchunk, part,
+                                       max_blocks, out, s);
 }
 
 // Persistent launch of a batched pass: the queue reset, then as many
