@@ -441,7 +441,11 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
     e = thiim::launch_fill_zero(c->F[0], 12 * L.S, c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "zero fields"));
     int flag = 0;
+    std::vector<thiim::PlaneCoef> planes(g->nz);
     e = hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(planes.data(), P, sizeof(thiim::PlaneCoef) * g->nz,
+                           hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "create sync"));
     if (flag) return bail(fail(THIIM_EINVAL, "eps has a non-finite value or eps' == 0"));
@@ -451,12 +455,34 @@ int thiim_create(const thiim_grid* g, const thiim_coeffs* m, double omega, void*
         if (e != hipSuccess) return bail(hip_fail(e, "complex64 coefficient launch"));
     }
 
-    // ||P Phi(0)||: one iteration from the zero state
-    e = residual_pass(c, 0, 1, c->stream);
-    if (e != hipSuccess) return bail(hip_fail(e, "phi(0) launch"));
+    // ||P Phi(0)||, one iteration from the zero state.  Phi(0) is zero except
+    // on the planes that carry a source (H = Src_H, E) and the plane below
+    // each (E reads H one plane up), so the residual pass runs on that range
+    // of planes only, as a grid of its own: the zero planes around it are
+    // what its z walls assume.
+    int smin = g->nz, smax = -1;
+    for (int k = 0; k < g->nz; ++k)
+        if (planes[k].has_src) {
+            smin = std::min(smin, k);
+            smax = std::max(smax, k);
+        }
     double r2 = 0, b2 = 0;
-    rc = read_out(c, &r2, &b2);
-    if (rc) return bail(rc);
+    if (smax >= 0) {
+        const int k0 = std::max(0, smin - 1), k1 = smax + 1;
+        const long long off = (long long)k0 * g->nx * g->ny;
+        thiim::CoefView v = c->cv;
+        if (v.C) v.C += off;
+        if (v.eps) v.eps += off;
+        v.src += off;
+        v.P += k0;
+        thiim::Geo gr = c->geo;
+        gr.nz = k1 - k0;
+        e = thiim::launch_fused_res(v, c->F[0] + off, c->F[1] + off, gr, c->tile_x, c->tile_y,
+                                    c->z_chunk, c->part, c->L.resid_max, c->out, c->stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "phi(0) launch"));
+        rc = read_out(c, &r2, &b2);
+        if (rc) return bail(rc);
+    }
     c->phi0_norm = std::sqrt(b2);
     if (!std::isfinite(c->phi0_norm)) return bail(fail(THIIM_EINVAL, "non-finite source response"));
     *out = c;
@@ -745,16 +771,21 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
                 int Kq = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau * T2));
                 if (Kq < 1) Kq = 1;
                 const int passes = (m + T2 - 1) / T2 > Kq ? (m + T2 - 1) / T2 : Kq;
+                // the last Kq passes sum their output into acc32 as they go; one
+                // FP64 kernel then adds the mean to lam
                 int di = 0;
                 for (int p = 0; e == hipSuccess && p < passes; ++p) {
+                    const int left = passes - p;
+                    const int acc_mode = left > Kq ? 0 : (left == Kq ? 1 : 2);
                     e = thiim::launch_adjoint32_blocked(c->cv, c->ce32, c->p32, c->d32[di],
-                                                        c->d32[1 - di], c->r32, c->geo, T2, 32,
-                                                        16, c->bz_chunk, c->stream);
+                                                        c->d32[1 - di], c->r32, c->acc32,
+                                                        acc_mode, c->geo, T2, 32, 16,
+                                                        c->bz_chunk, c->stream);
                     di = 1 - di;
-                    if (e == hipSuccess && p >= passes - Kq)
-                        e = thiim::launch_accum(c->lam[0], c->d32[di], 1.0 / Kq, nullptr, 0, S,
-                                                N, c->stream);
                 }
+                if (e == hipSuccess)
+                    e = thiim::launch_accum(c->lam[0], c->acc32, 1.0 / Kq, nullptr, 0, S, N,
+                                            c->stream);
                 done += passes * T2 - m;  // counted below as m
             } else {
                 if (e == hipSuccess)

@@ -169,9 +169,12 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
                             int tile_x, int tile_y, int kchunk, hipStream_t s);
 // T = 2 transposed iterations per pass (regions of 32 x 16 columns) of the
 // same complex64 sweep; chunk planes per workgroup stream
+// acc_mode 1 writes the pass's output also to acc, 2 adds it to acc (12
+// complex64 arrays), 0 leaves acc alone.
 hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                                    const float2* A, float2* B, const float2* R, const Geo& g,
-                                    int T, int rx, int ry, int kchunk, hipStream_t s);
+                                    const float2* A, float2* B, const float2* R, float2* acc,
+                                    int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
+                                    hipStream_t s);
 // 12-array FP64 helpers: Y -= X; X += w D.
 hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s);
 hipError_t launch_to32(const double2* X, float2* R, long long S, long long N, hipStream_t s);

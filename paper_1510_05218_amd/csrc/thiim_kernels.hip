@@ -2007,8 +2007,11 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V*
 // cell's arithmetic is k_adjoint's, operation for operation; what a stage
 // hands to the next plane or the next stage stays in registers: t_E lam_E,
 // the z parts of u and v, lam_H, the coefficient record and the source.
+// ACC: the stored lam of every cell is also summed into ap.p.acc (12
+// complex64 arrays): written by acc_mode 1, added to by acc_mode 2 -- the
+// window sum of the defect correction, formed without a pass of its own.
 // ---------------------------------------------------------------------------
-template <int RX, int RY, int T>
+template <int RX, int RY, int T, bool ACC>
 __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
                                                               const float2* __restrict__ A,
                                                               float2* __restrict__ B,
@@ -2046,6 +2049,15 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
     V* BE = B + 6 * S;
     const V* GE = G + 6 * S;
     const V Z = vzero<V>();
+    // ACC: six parts into the window sum at plane offset po
+    auto acc6 = [&](V* __restrict__ acc, long long po, const V v[6]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            V w = v[q];
+            if (ap.p.acc_mode == 2) w = cadd(ldo(acc + q * S + po, bo), w);
+            sto(acc + q * S + po, bo, w);
+        }
+    };
 
     for (int i = threadIdx.x; i < T * 4 * R; i += R) {
         (&U[0][0][0])[i] = Z;
@@ -2135,7 +2147,10 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
                     v[q] = cmul(c[q], lh);
                     ho[q] = cadd(cmul(t[q], lh), s == 1 ? gH0[q] : gh[s - 1][q]);
                 }
-                if (s == T && own && kh >= k0 && kh < k1) store6v(B, S, kh * plane, bo, ho);
+                if (s == T && own && kh >= k0 && kh < k1) {
+                    store6v(B, S, kh * plane, bo, ho);
+                    if constexpr (ACC) acc6(ap.p.acc, kh * plane, ho);
+                }
             }
             // ---- phase 3: lam_E = t_E lam_E + D_H^T v at plane ke
             V eout[6];
@@ -2151,7 +2166,10 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
 #pragma unroll
                 for (int q = 0; q < 6; ++q)
                     eout[q] = cadd(cadd(ep[s - 1][q], inc[q / 2]), s == 1 ? gE0[q] : ge[s - 1][q]);
-                if (s == T && own && ke >= k0 && ke < k1) store6v(BE, S, ke * plane, bo, eout);
+                if (s == T && own && ke >= k0 && ke < k1) {
+                    store6v(BE, S, ke * plane, bo, eout);
+                    if constexpr (ACC) acc6(ap.p.acc + 6 * S, ke * plane, eout);
+                }
             }
             // v of plane kh for phase 3 of the next step (the other parity)
             W[s - 1][par][0][me] = v[1];
@@ -2776,15 +2794,17 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
 }
 
 hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                                    const float2* A, float2* B, const float2* R, const Geo& g,
-                                    int T, int rx, int ry, int kchunk, hipStream_t s) {
+                                    const float2* A, float2* B, const float2* R, float2* acc,
+                                    int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
+                                    hipStream_t s) {
     if (!cv.compact || T != 2 || rx != 32 || ry != 16) return hipErrorInvalidValue;
+    if (acc_mode < 0 || acc_mode > 2 || (acc_mode && !acc)) return hipErrorInvalidValue;
     AdjPol32 ap;
     ap.p.ce = ce;
     ap.p.P32 = P32;
     ap.p.r = nullptr;
-    ap.p.acc = nullptr;
-    ap.p.acc_mode = 0;
+    ap.p.acc = acc;
+    ap.p.acc_mode = acc_mode;
     ap.p.S = cv.S;
     ap.p.ph = to32(cv.K.ph);
     ap.p.phc = to32(cv.K.phc);
@@ -2792,8 +2812,12 @@ hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const 
     ap.p.ph2c = to32(cv.K.ph2c);
     const int ox = rx - 2 * T, oy = ry - 2 * T;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
-    hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2>), grid, dim3(512), 0, s, ap, A, B, R, g,
-                       kchunk);
+    if (acc_mode)
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, true>), grid, dim3(512), 0, s, ap, A,
+                           B, R, g, kchunk);
+    else
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, false>), grid, dim3(512), 0, s, ap, A,
+                           B, R, g, kchunk);
     return hipGetLastError();
 }
 

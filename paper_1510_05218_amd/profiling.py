@@ -57,6 +57,9 @@ ALG_BYTES_PER_CELL = {
     "k_naive_e<CompactCoefs>": 304,          # + eps
     "k_fused<64,8,FullCoefs>": 768,          # 24 t/c + 12 read, 12 written
     "k_fused<64,8,CompactCoefs>": 400,       # eps + 12 read, 12 written
+    # (k_fused_res, the fused pass that forms the residual on the way, moves
+    # the same bytes per cell, but thiim_create also launches it on the few
+    # planes a source reaches: its average launch covers no fixed cell count)
     # full storage: each stage reads its planes' 24 t/c arrays
     "k_blocked<64,8,2,Pol64<FullCoefs>>": 1152,
     "k_blocked<32,16,2,Pol64<CompactCoefs>>": 400,
@@ -71,6 +74,10 @@ ALG_BYTES_PER_CELL = {
     # complex64 transposed inner sweep: 12 lam + 16 B record + 12 G read,
     # 12 lam written
     "k_adjoint<64,8,AdjPol32>": 304,
+    # its two-iteration blocked form (per pass), and the instance that also
+    # sums the stored lam into the window accumulator (+ 12 read, 12 written)
+    "k_adjoint32_blocked<32,16,2,false>": 304,
+    "k_adjoint32_blocked<32,16,2,true>": 496,
     # complex64 inner sweeps (8 B per value) in pair-sum form: per H and E
     # side 3 d + 3 r read and 3 d written where the split pairs are symmetric,
     # 5 of each on the PML planes, + the 16 B record: 160 B off the PML, 162

@@ -68,6 +68,38 @@ def test_residual_matches_fields(shape, tile, zc, bc):
     assert abs(rel - ref) <= 1e-12 * ref, (rel, ref)
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+def test_phi0_of_a_plane_source(bc):
+    """thiim_create forms ||P Phi(0)|| on the planes that a source can reach
+    in one iteration (here the plane source and the plane below it) as a grid
+    of its own: it must equal the norm over the whole Phi(0)."""
+    _require_gpu()
+    print(f"[residual] plane source, bc {bc}", flush=True)
+    pb = inputs.solar_cell(40, 36, 48, seed=5, npml=6)
+    pb.bcx = pb.bcy = bc
+    srcs = [v for v in pb.sources.values()]
+    planes = sorted({int(k) for v in srcs for k in np.nonzero(np.abs(v).sum(axis=(1, 2)))[0]})
+    assert 0 < len(planes) < 4  # a plane source, far from the walls
+    s = thiim.Solver(pb, kernel="fused", storage="compact")
+    x = torch.zeros((12, 48, 36, 40), dtype=torch.complex128, device="cuda")
+    s.set_fields(x)
+    s.iterate(1)
+    s.stream.synchronize()
+    phi = s.fields().clone()
+    phi0 = _pnorm(phi)
+    nz_planes = sorted({int(k) for k in torch.nonzero(
+        (phi[0::2] + phi[1::2]).abs().sum(dim=(0, 2, 3))).flatten().tolist()})
+    assert nz_planes and nz_planes[0] >= planes[0] - 1 and nz_planes[-1] <= planes[-1]
+    # residual of x = Phi(0) is ||P(Phi(Phi(0)) - Phi(0))|| / ||P Phi(0)||
+    s.iterate(1)
+    s.stream.synchronize()
+    ref = _pnorm(s.fields() - phi) / phi0
+    s.set_fields(phi)
+    rel = s.residual()
+    s.close()
+    assert abs(rel - ref) <= 1e-12 * ref, (rel, ref)
+
+
 def test_residual_after_iterations_matches_blocked_and_naive():
     """The same residual from contexts whose iterations run the blocked and
     the naive sweeps: their iterates are bit-identical and the residual pass
