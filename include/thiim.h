@@ -276,8 +276,9 @@ int thiim_batch_create(thiim_ctx *const *ctxs, int n, void *workspace,
  * per device, held until the process ends), so n <= 128 (THIIM_EINVAL
  * beyond).  All contexts must be on one device; the first call on a device
  * looks up the array's address there.  One such batch per device at a time:
- * the array keeps the last batch's tables (re-uploaded by every new batch,
- * the queue counters reset before every pass), so a second call on a device
+ * the array keeps the last batch's tables (re-uploaded by every new batch;
+ * the queue counters are zeroed when the batch is made and every pass leaves
+ * them zero), so a second call on a device
  * whose static batch is still alive fails with THIIM_EINVAL; destroy the
  * first (thiim_batch_destroy, which then waits for the batch's stream).
  * Calls on one batch from several threads at once race, as for any batch.

@@ -1066,7 +1066,7 @@ constexpr size_t batch_items_bytes(int n) {
 constexpr size_t batch_items32_bytes(int n) {
     return align_up((size_t)2 * n * sizeof(thiim::BatchItem32), kAlign);
 }
-// item arrays (both kinds), then the 8 counters of the device work queue
+// item arrays (both kinds), then the 9 counters of the device work queue
 constexpr size_t batch_bytes(int n) {
     return batch_items_bytes(n) + batch_items32_bytes(n) + kAlign;
 }
@@ -1464,6 +1464,11 @@ int make_batch(thiim_ctx* const* ctxs, int n, char* ws, size_t ws_bytes, int sta
     b->exec = nullptr;
     b->graph_iters = kGraphIters;
     b->static_dev = static_dev;
+    const hipError_t e = thiim::launch_queue_reset(b->queue, b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch: queue reset");
+    }
     *out = b;
     return THIIM_OK;
 }

@@ -139,8 +139,12 @@ hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long 
 // Batched passes over nitems problems whose tiles total `total` (items in
 // device memory, ordered by tile_begin): persistent launches of at most the
 // resident workgroups (ncu CUs) that take tiles from a device work queue of
-// 8 counters at `queue` (reset by the launcher; launches sharing a queue must
-// be ordered on one stream).
+// 9 counters at `queue` (zero before the first pass, see launch_queue_reset;
+// every pass leaves them zero again; launches sharing a queue must be ordered
+// on one stream).
+// Zeroes the counters of a batch's device work queue (once, when the batch is
+// made: every persistent pass leaves them zero for the next).
+hipError_t launch_queue_reset(unsigned int* queue, hipStream_t s);
 hipError_t launch_fused_batch(const BatchItem* items, int nitems, int total, int tile_x,
                               int tile_y, unsigned int* queue, int ncu, hipStream_t s);
 hipError_t launch_blocked_batch(const BatchItem* items, int nitems, int total, int T, int rx,

@@ -1597,9 +1597,13 @@ __device__ __forceinline__ Tile batch_tile(const Item& it, int t) {
 // workgroups to the XCDs in turn) and, once that range is empty, of the
 // following ranges; it returns when all eight are empty.  Tiles of one pass
 // do not depend on each other, so no workgroup ever waits for another, and
-// every counter grows by at most total + workgroups per launch.
+// every counter grows by at most total + workgroups per launch.  queue[8]
+// counts the workgroups that have left; the last one zeroes all nine, so a
+// pass leaves the queue ready for the next (k_queue_reset zeroes it once,
+// when the batch is made).
+constexpr int kQueueCounters = 9;
 __global__ void k_queue_reset(unsigned int* __restrict__ queue) {
-    if (threadIdx.x < 8) queue[threadIdx.x] = 0u;
+    if (threadIdx.x < kQueueCounters) queue[threadIdx.x] = 0u;
 }
 
 template <class Body>
@@ -1624,6 +1628,14 @@ __device__ __forceinline__ void run_queue(unsigned int* __restrict__ queue, int 
         }
         body(t);
         __syncthreads();  // the next tile reuses the LDS
+    }
+    // the last workgroup to leave clears the counters for the next pass: by
+    // then every other workgroup has made its last claim (each claim returns
+    // before its workgroup counts itself out)
+    if (threadIdx.x == 0) {
+        const unsigned int out = atomicAdd(queue + 8, 1u);
+        if (out == gridDim.x - 1)
+            for (int i = 0; i < kQueueCounters; ++i) atomicExch(queue + i, 0u);
     }
 }
 
@@ -2670,11 +2682,9 @@ static hipError_t launch_queued(int block, const Item* items, int nitems, int to
                                 unsigned int* queue, int ncu, hipStream_t s) {
     const long long resident = (long long)blocks_per_cu<K>(block) * (ncu > 0 ? ncu : 256);
     const int grid = (int)(total < resident ? total : resident);
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     void* args[] = {(void*)&items, (void*)&nitems, (void*)&total, (void*)&queue};
-    e = hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
+    hipError_t e =
+        hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -2713,11 +2723,9 @@ static hipError_t launch_queued_pass(int block, const BatchItem32* items, int ni
                                      int left, unsigned int* queue, int ncu, hipStream_t s) {
     const long long resident = (long long)blocks_per_cu<K>(block) * (ncu > 0 ? ncu : 256);
     const int grid = (int)(total < resident ? total : resident);
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     void* args[] = {(void*)&items, (void*)&nitems, (void*)&total, (void*)&left, (void*)&queue};
-    e = hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
+    hipError_t e =
+        hipLaunchKernel(reinterpret_cast<const void*>(K), dim3(grid), dim3(block), args, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -2987,6 +2995,11 @@ hipError_t launch_stream_probe(const double2* in, double2* out, long long S, lon
         hipLaunchKernelGGL((k_stream_probe<13, 12>), dim3(grid), dim3(256), 0, s, in, out, S, n);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(unsigned int* queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
     return hipGetLastError();
 }
 
