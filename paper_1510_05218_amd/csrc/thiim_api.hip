@@ -766,8 +766,24 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
                 // transposed sweep, averaged over the passes of one rotation
                 // period; the defect and lam in FP64
                 if (e == hipSuccess) e = thiim::launch_to32(c->lam[1], c->r32, S, N, c->stream);
-                if (e == hipSuccess) e = thiim::launch_copy32(c->r32, c->d32[0], S, N, c->stream);
                 constexpr int T2 = 2;
+                // the passes add G_T = (I + M^T) r at their last stage: one pass
+                // with source r at both stages from d = 0 (into rt32, free while
+                // the adjoint runs)
+                if (e == hipSuccess)
+                    e = thiim::launch_fill_zero((double2*)c->d32[1], 6 * S, c->stream);
+                if (e == hipSuccess)
+                    e = thiim::launch_adjoint32_blocked(c->cv, c->ce32, c->p32, c->d32[1],
+                                                        c->rt32, c->r32, false, nullptr, 0,
+                                                        c->geo, T2, 32, 16, c->bz_chunk,
+                                                        c->stream);
+                if (e == hipSuccess) e = thiim::launch_copy32(c->r32, c->d32[0], S, N, c->stream);
+                // the passes' z chunk, for their 32 x 24 regions
+                constexpr int aox = 32 - 2 * T2, aoy = 24 - 2 * T2;
+                const long long atiles =
+                    (long long)((c->g.nx + aox - 1) / aox) * ((c->g.ny + aoy - 1) / aoy);
+                const int achunk =
+                    c->g.z_chunk > 0 ? c->g.z_chunk : auto_chunk(c->g, atiles, c->ncu);
                 int Kq = (int)std::lround(2.0 * M_PI / (c->omega * c->g.tau * T2));
                 if (Kq < 1) Kq = 1;
                 const int passes = (m + T2 - 1) / T2 > Kq ? (m + T2 - 1) / T2 : Kq;
@@ -778,9 +794,9 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
                     const int left = passes - p;
                     const int acc_mode = left > Kq ? 0 : (left == Kq ? 1 : 2);
                     e = thiim::launch_adjoint32_blocked(c->cv, c->ce32, c->p32, c->d32[di],
-                                                        c->d32[1 - di], c->r32, c->acc32,
-                                                        acc_mode, c->geo, T2, 32, 16,
-                                                        c->bz_chunk, c->stream);
+                                                        c->d32[1 - di], c->rt32, true, c->acc32,
+                                                        acc_mode, c->geo, T2, 32, 24, achunk,
+                                                        c->stream);
                     di = 1 - di;
                 }
                 if (e == hipSuccess)

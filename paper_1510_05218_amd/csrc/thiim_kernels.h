@@ -174,11 +174,13 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
 // T = 2 transposed iterations per pass (regions of 32 x 16 columns) of the
 // same complex64 sweep; chunk planes per workgroup stream
 // acc_mode 1 writes the pass's output also to acc, 2 adds it to acc (12
-// complex64 arrays), 0 leaves acc alone.
+// complex64 arrays), 0 leaves acc alone.  Regions 32 x 16 with the source R
+// at every stage (src_last false), or 32 x 24 at three waves per SIMD with R
+// = G_T = (I + M^T) G entering at the last stage only (src_last true).
 hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                                    const float2* A, float2* B, const float2* R, float2* acc,
-                                    int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
-                                    hipStream_t s);
+                                    const float2* A, float2* B, const float2* R, bool src_last,
+                                    float2* acc, int acc_mode, const Geo& g, int T, int rx,
+                                    int ry, int kchunk, hipStream_t s);
 // 12-array FP64 helpers: Y -= X; X += w D.
 hipError_t launch_sub(const double2* X, double2* Y, long long S, long long N, hipStream_t s);
 hipError_t launch_to32(const double2* X, float2* R, long long S, long long N, hipStream_t s);

@@ -2022,9 +2022,13 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V*
 // ACC: the stored lam of every cell is also summed into ap.p.acc (12
 // complex64 arrays): written by acc_mode 1, added to by acc_mode 2 -- the
 // window sum of the defect correction, formed without a pass of its own.
+// SRC_LAST: G is G_T = (I + M^T + ... + M^{T-1}) G' and enters at the last
+// stage only (T iterations with source G' map lam to (M^T)^T lam + G_T); its
+// two planes are read at the top of the step and nothing of it is carried.
+// G_T is one pass with source G' at every stage from lam = 0.
 // ---------------------------------------------------------------------------
-template <int RX, int RY, int T, bool ACC>
-__global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
+template <int RX, int RY, int T, bool ACC, bool SRC_LAST>
+__global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_blocked(AdjPol32 ap,
                                                               const float2* __restrict__ A,
                                                               float2* __restrict__ B,
                                                               const float2* __restrict__ G,
@@ -2110,10 +2114,15 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
         if (k < g.nz && valid) {
             load6v(AE, S, k * plane, bo, lE);
             load6v(A, S, k * plane, bo, lH);
-            load6v(G, S, k * plane, bo, gH0);
+            if constexpr (!SRC_LAST) load6v(G, S, k * plane, bo, gH0);
             r0 = ap.p.load_crec(k * plane, bo);
         }
-        if (valid && k >= 1 && k - 1 < g.nz) load6v(GE, S, (k - 1) * plane, bo, gE0);
+        // the source of the H parts at plane kh and of the E parts at plane
+        // ke of the stage that adds it (stage 1, or the last with SRC_LAST)
+        constexpr int GS = SRC_LAST ? T : 1;
+        if (SRC_LAST && valid && k - GS + 1 >= 0 && k - GS + 1 < g.nz)
+            load6v(G, S, (k - GS + 1) * plane, bo, gH0);
+        if (valid && k - GS >= 0 && k - GS < g.nz) load6v(GE, S, (k - GS) * plane, bo, gE0);
 
         V eo[6];  // lam_E handed from stage s to stage s + 1 (plane ke)
         V hn[T][6], en_n[T][6], u0n[T], u2n[T], v0n[T], v2n[T];
@@ -2157,7 +2166,10 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
                 for (int q = 0; q < 6; ++q) {
                     const V lh = cadd(s == 1 ? lH[q] : hc[s - 1][q], inc[q / 2]);
                     v[q] = cmul(c[q], lh);
-                    ho[q] = cadd(cmul(t[q], lh), s == 1 ? gH0[q] : gh[s - 1][q]);
+                    if constexpr (SRC_LAST)
+                        ho[q] = s == T ? cadd(cmul(t[q], lh), gH0[q]) : cmul(t[q], lh);
+                    else
+                        ho[q] = cadd(cmul(t[q], lh), s == 1 ? gH0[q] : gh[s - 1][q]);
                 }
                 if (s == T && own && kh >= k0 && kh < k1) {
                     store6v(B, S, kh * plane, bo, ho);
@@ -2176,8 +2188,14 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
                     csub(csub(W[s - 1][pq][1][me], W[s - 1][pq][1][xp]),
                          csub(W[s - 1][pq][0][me], W[s - 1][pq][0][yp]))};
 #pragma unroll
-                for (int q = 0; q < 6; ++q)
-                    eout[q] = cadd(cadd(ep[s - 1][q], inc[q / 2]), s == 1 ? gE0[q] : ge[s - 1][q]);
+                for (int q = 0; q < 6; ++q) {
+                    if constexpr (SRC_LAST)
+                        eout[q] = s == T ? cadd(cadd(ep[s - 1][q], inc[q / 2]), gE0[q])
+                                         : cadd(ep[s - 1][q], inc[q / 2]);
+                    else
+                        eout[q] = cadd(cadd(ep[s - 1][q], inc[q / 2]),
+                                       s == 1 ? gE0[q] : ge[s - 1][q]);
+                }
                 if (s == T && own && ke >= k0 && ke < k1) {
                     store6v(BE, S, ke * plane, bo, eout);
                     if constexpr (ACC) acc6(ap.p.acc + 6 * S, ke * plane, eout);
@@ -2206,8 +2224,10 @@ __global__ __launch_bounds__(RX* RY) void k_adjoint32_blocked(AdjPol32 ap,
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 hc[s][q] = hn[s - 1][q];
-                gh[s][q] = s == 1 ? gH0[q] : gh[s - 1][q];
-                ge[s][q] = s == 1 ? gE0[q] : ge[s - 1][q];
+                if constexpr (!SRC_LAST) {
+                    gh[s][q] = s == 1 ? gH0[q] : gh[s - 1][q];
+                    ge[s][q] = s == 1 ? gE0[q] : ge[s - 1][q];
+                }
             }
         }
 #pragma unroll
@@ -2802,11 +2822,12 @@ hipError_t launch_adjoint32(const CoefView& cv, const float4* ce, const PlaneCoe
 }
 
 hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const PlaneCoef32* P32,
-                                    const float2* A, float2* B, const float2* R, float2* acc,
-                                    int acc_mode, const Geo& g, int T, int rx, int ry, int kchunk,
-                                    hipStream_t s) {
-    if (!cv.compact || T != 2 || rx != 32 || ry != 16) return hipErrorInvalidValue;
+                                    const float2* A, float2* B, const float2* R, bool src_last,
+                                    float2* acc, int acc_mode, const Geo& g, int T, int rx,
+                                    int ry, int kchunk, hipStream_t s) {
+    if (!cv.compact || T != 2 || rx != 32 || (ry != 16 && ry != 24)) return hipErrorInvalidValue;
     if (acc_mode < 0 || acc_mode > 2 || (acc_mode && !acc)) return hipErrorInvalidValue;
+    if (src_last != (ry == 24)) return hipErrorInvalidValue;
     AdjPol32 ap;
     ap.p.ce = ce;
     ap.p.P32 = P32;
@@ -2820,12 +2841,20 @@ hipError_t launch_adjoint32_blocked(const CoefView& cv, const float4* ce, const 
     ap.p.ph2c = to32(cv.K.ph2c);
     const int ox = rx - 2 * T, oy = ry - 2 * T;
     dim3 grid(((g.nx + ox - 1) / ox) * ((g.ny + oy - 1) / oy) * nchunks(g, kchunk));
-    if (acc_mode)
-        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, true>), grid, dim3(512), 0, s, ap, A,
-                           B, R, g, kchunk);
+    if (ry == 16 && acc_mode)
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, true, false>), grid, dim3(512), 0, s,
+                           ap, A, B, R, g, kchunk);
+    else if (ry == 16)
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, false, false>), grid, dim3(512), 0, s,
+                           ap, A, B, R, g, kchunk);
+    else if (src_last && acc_mode)
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 24, 2, true, true>), grid, dim3(768), 0, s,
+                           ap, A, B, R, g, kchunk);
+    else if (src_last)
+        hipLaunchKernelGGL((k_adjoint32_blocked<32, 24, 2, false, true>), grid, dim3(768), 0, s,
+                           ap, A, B, R, g, kchunk);
     else
-        hipLaunchKernelGGL((k_adjoint32_blocked<32, 16, 2, false>), grid, dim3(512), 0, s, ap, A,
-                           B, R, g, kchunk);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
