@@ -257,7 +257,8 @@ int thiim_apply_tuning(thiim_ctx *ctx, const thiim_tuning *tuning);
  * one common stream, each context's own sweep configuration).  Contexts with
  * the same configuration share one persistent launch per pass: the resident
  * workgroups take the concatenated tiles of all of them from a device work
- * queue (one counter per XCD, reset before each pass).  The passes of each
+ * queue (one counter per XCD; the last workgroup of a pass clears them for
+ * the next).  The passes of each
  * 64 iterations are captured once in a HIP graph and replayed (eager
  * launches on the null stream, which cannot be captured).  A batch borrows
  * its contexts and a small device workspace (the per-launch item tables and

@@ -2022,10 +2022,11 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V*
 // ACC: the stored lam of every cell is also summed into ap.p.acc (12
 // complex64 arrays): written by acc_mode 1, added to by acc_mode 2 -- the
 // window sum of the defect correction, formed without a pass of its own.
-// SRC_LAST: G is G_T = (I + M^T + ... + M^{T-1}) G' and enters at the last
-// stage only (T iterations with source G' map lam to (M^T)^T lam + G_T); its
-// two planes are read at the top of the step and nothing of it is carried.
-// G_T is one pass with source G' at every stage from lam = 0.
+// SRC_LAST: G is G_T, the sum of M^T applied 0 .. T-1 times to a source G',
+// and enters at the last stage only (T iterations lam <- M^T lam + G' equal
+// T applications of M^T to lam plus G_T); its two planes are read at the top
+// of the step and nothing of it is carried.  G_T is one pass with source G'
+// at every stage from lam = 0.
 // ---------------------------------------------------------------------------
 template <int RX, int RY, int T, bool ACC, bool SRC_LAST>
 __global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_blocked(AdjPol32 ap,
@@ -2681,9 +2682,9 @@ hipError_t launch_fused_res(const CoefView& cv, const double2* A, double2* B, co
                                        max_blocks, out, s);
 }
 
-// Persistent launch of a batched pass: the queue reset, then as many
-// workgroups as the device holds at once (the kernel's occupancy times the
-// CUs), at most one per tile.
+// Persistent launch of a batched pass: as many workgroups as the device
+// holds at once (the kernel's occupancy times the CUs), at most one per tile;
+// the queue is zero on entry and left zero by the last workgroup.
 template <auto K>
 static int blocks_per_cu(int block) {
     static const int nb = [block] {
