@@ -628,7 +628,7 @@ int solve_mixed(thiim_ctx* c, double tol, int max_it, int inner, int* iters, dou
         }
         // x += (window sum) / Kp in FP64
         if (e == hipSuccess)
-            e = thiim::launch_accum(c->F[c->cur], c->acc32, 1.0 / Kp, c->cv.P,
+            e = thiim::launch_accum(c->F[c->cur], c->acc32, 1.0 / Kp, c->cv.P, 0.5,
                                     (long long)c->g.nx * c->g.ny, c->L.S, c->L.N, c->stream);
         if (e != hipSuccess) return hip_fail(e, "mixed: inner sweeps");
         done += passes * T;           // sweeps run (d = r is a copy)
@@ -800,7 +800,8 @@ int thiim_adjoint_grad(thiim_ctx* c, const double* weight, double tol, int max_i
                     di = 1 - di;
                 }
                 if (e == hipSuccess)
-                    e = thiim::launch_accum(c->lam[0], c->acc32, 1.0 / Kq, nullptr, 0, S, N,
+                    e = thiim::launch_accum(c->lam[0], c->acc32, 1.0 / Kq, c->cv.P, 1.0,
+                                            (long long)c->g.nx * c->g.ny, S, N,
                                             c->stream);
                 done += passes * T2 - m;  // counted below as m
             } else {
@@ -1400,8 +1401,8 @@ int batch_solve_mixed(thiim_batch* b, double tol, int max_it, int m_user,
                     if (err != hipSuccess) break;
                     thiim_ctx* c = b->ctx[i];
                     err = thiim::launch_accum(c->F[c->cur], c->acc32, 1.0 / Kp[i], c->cv.P,
-                                              (long long)c->g.nx * c->g.ny, c->L.S, c->L.N,
-                                              b->stream);
+                                              0.5, (long long)c->g.nx * c->g.ny, c->L.S,
+                                              c->L.N, b->stream);
                 }
             }
             return err;

@@ -130,10 +130,12 @@ hipError_t launch_inner32(const CoefView& cv, const float4* ce, const PlaneCoef3
 hipError_t launch_defect(const double2* A, const double2* B, float2* R, const PlaneCoef* P,
                          long long S, long long N, long long nxy, double* part, int nblk,
                          double* out, hipStream_t s);
-// x += w d; with a plane table P (nxy cells per plane), d in the pair-sum
-// form of the complex64 inner sweeps; P = nullptr: d holds all 12 parts
+// x += w d; with a plane table P (nxy cells per plane) a symmetric pair of d
+// is stored as its first part and each part of the pair receives share * w
+// times it (1/2: the pair-sum form of the forward inner sweeps, 1: the
+// pair-equal form of the transposed ones); P = nullptr: d holds all 12 parts
 hipError_t launch_accum(double2* X, const float2* D, double w, const PlaneCoef* P,
-                        long long nxy, long long S, long long N, hipStream_t s);
+                        double share, long long nxy, long long S, long long N, hipStream_t s);
 hipError_t launch_copy32(const float2* src, float2* dst, long long S, long long N,
                          hipStream_t s);
 // Batched passes over nitems problems whose tiles total `total` (items in

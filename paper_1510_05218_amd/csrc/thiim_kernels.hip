@@ -2022,6 +2022,12 @@ __global__ __launch_bounds__(TX* TY) void k_adjoint(AP ap, const typename AP::V*
 // ACC: the stored lam of every cell is also summed into ap.p.acc (12
 // complex64 arrays): written by acc_mode 1, added to by acc_mode 2 -- the
 // window sum of the defect correction, formed without a pass of its own.
+// Pair-equal form: where the two parts of a split pair have identical
+// coefficients (the z pair always, the x and y pairs off the PML: the plane
+// flags of the complex64 records) they receive identical increments, and the
+// transposed system's sources give both the same value, so from lam = 0 the
+// two parts stay equal; such a pair is read, written and summed as its first
+// part only, and the second part is a copy in registers.
 // SRC_LAST: G is G_T, the sum of M^T applied 0 .. T-1 times to a source G',
 // and enters at the last stage only (T iterations lam <- M^T lam + G' equal
 // T applications of M^T to lam plus G_T); its two planes are read at the top
@@ -2066,15 +2072,42 @@ __global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_bloc
     V* BE = B + 6 * S;
     const V* GE = G + 6 * S;
     const V Z = vzero<V>();
-    // ACC: six parts into the window sum at plane offset po
-    auto acc6 = [&](V* __restrict__ acc, long long po, const V v[6]) {
+    // six parts of a plane in pair-equal form (sym: the x and y pairs of this
+    // side of the plane are symmetric; the z pair always is)
+    auto load_eq = [&](const V* __restrict__ F, bool sym, long long po, V v[6]) {
+        v[0] = ldo(F + 0 * S + po, bo);
+        v[2] = ldo(F + 2 * S + po, bo);
+        v[4] = ldo(F + 4 * S + po, bo);
+        v[5] = v[4];
+        if (sym) {
+            v[1] = v[0];
+            v[3] = v[2];
+        } else {
+            v[1] = ldo(F + 1 * S + po, bo);
+            v[3] = ldo(F + 3 * S + po, bo);
+        }
+    };
+    auto store_eq = [&](V* __restrict__ F, bool sym, long long po, const V v[6]) {
+        sto(F + 0 * S + po, bo, v[0]);
+        sto(F + 2 * S + po, bo, v[2]);
+        sto(F + 4 * S + po, bo, v[4]);
+        if (!sym) {
+            sto(F + 1 * S + po, bo, v[1]);
+            sto(F + 3 * S + po, bo, v[3]);
+        }
+    };
+    // ACC: the stored parts into the window sum at plane offset po
+    auto acc6 = [&](V* __restrict__ acc, bool sym, long long po, const V v[6]) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
+            if (q == 5 || (sym && (q == 1 || q == 3))) continue;
             V w = v[q];
             if (ap.p.acc_mode == 2) w = cadd(ldo(acc + q * S + po, bo), w);
             sto(acc + q * S + po, bo, w);
         }
     };
+    auto hsym = [&](int k) { return ap.p.P32[k].hsym != 0; };
+    auto esym = [&](int k) { return ap.p.P32[k].esym != 0; };
 
     for (int i = threadIdx.x; i < T * 4 * R; i += R) {
         (&U[0][0][0])[i] = Z;
@@ -2113,17 +2146,18 @@ __global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_bloc
         for (int q = 0; q < 6; ++q) lE[q] = lH[q] = gH0[q] = gE0[q] = Z;
         float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (k < g.nz && valid) {
-            load6v(AE, S, k * plane, bo, lE);
-            load6v(A, S, k * plane, bo, lH);
-            if constexpr (!SRC_LAST) load6v(G, S, k * plane, bo, gH0);
+            load_eq(AE, esym(k), k * plane, lE);
+            load_eq(A, hsym(k), k * plane, lH);
+            if constexpr (!SRC_LAST) load_eq(G, hsym(k), k * plane, gH0);
             r0 = ap.p.load_crec(k * plane, bo);
         }
         // the source of the H parts at plane kh and of the E parts at plane
         // ke of the stage that adds it (stage 1, or the last with SRC_LAST)
         constexpr int GS = SRC_LAST ? T : 1;
         if (SRC_LAST && valid && k - GS + 1 >= 0 && k - GS + 1 < g.nz)
-            load6v(G, S, (k - GS + 1) * plane, bo, gH0);
-        if (valid && k - GS >= 0 && k - GS < g.nz) load6v(GE, S, (k - GS) * plane, bo, gE0);
+            load_eq(G, hsym(k - GS + 1), (k - GS + 1) * plane, gH0);
+        if (valid && k - GS >= 0 && k - GS < g.nz)
+            load_eq(GE, esym(k - GS), (k - GS) * plane, gE0);
 
         V eo[6];  // lam_E handed from stage s to stage s + 1 (plane ke)
         V hn[T][6], en_n[T][6], u0n[T], u2n[T], v0n[T], v2n[T];
@@ -2173,8 +2207,8 @@ __global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_bloc
                         ho[q] = cadd(cmul(t[q], lh), s == 1 ? gH0[q] : gh[s - 1][q]);
                 }
                 if (s == T && own && kh >= k0 && kh < k1) {
-                    store6v(B, S, kh * plane, bo, ho);
-                    if constexpr (ACC) acc6(ap.p.acc, kh * plane, ho);
+                    store_eq(B, hsym(kh), kh * plane, ho);
+                    if constexpr (ACC) acc6(ap.p.acc, hsym(kh), kh * plane, ho);
                 }
             }
             // ---- phase 3: lam_E = t_E lam_E + D_H^T v at plane ke
@@ -2198,8 +2232,8 @@ __global__ __launch_bounds__(RX* RY, RX* RY > 512 ? 3 : 1) void k_adjoint32_bloc
                                        s == 1 ? gE0[q] : ge[s - 1][q]);
                 }
                 if (s == T && own && ke >= k0 && ke < k1) {
-                    store6v(BE, S, ke * plane, bo, eout);
-                    if constexpr (ACC) acc6(ap.p.acc + 6 * S, ke * plane, eout);
+                    store_eq(BE, esym(ke), ke * plane, eout);
+                    if constexpr (ACC) acc6(ap.p.acc + 6 * S, esym(ke), ke * plane, eout);
                 }
             }
             // v of plane kh for phase 3 of the next step (the other parity)
@@ -2429,12 +2463,14 @@ __global__ __launch_bounds__(256) void k_defect_partial(const double2* __restric
 }
 
 // x += w d (complex64 correction accumulated in FP64), all 12 arrays.  With
-// a plane table P, d is in the pair-sum form of the complex64 inner sweeps
-// (a symmetric pair is (sum, 0), its second part not stored) and each part
-// of such a pair receives w sum / 2; without, d holds all 12 parts.
+// a plane table P, a symmetric pair of d is stored as its first part only and
+// each part of the pair receives share * w * (that value): share 1/2 for the
+// pair-sum form of the forward inner sweeps (the pair's sum), 1 for the
+// pair-equal form of the transposed ones (both parts equal); without P, d
+// holds all 12 parts.
 __global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, double w,
-                        const PlaneCoef* __restrict__ P, long long nxy, long long S,
-                        long long N) {
+                        const PlaneCoef* __restrict__ P, double share, long long nxy,
+                        long long S, long long N) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
         bool hsym = false, esym = false;
@@ -2449,7 +2485,7 @@ __global__ void k_accum(double2* __restrict__ X, const float2* __restrict__ D, d
             const double2 x0 = X[(2 * c) * S + p], x1 = X[(2 * c + 1) * S + p];
             const float2 d0 = D[(2 * c) * S + p];
             if (sym) {
-                const double hw = 0.5 * w;
+                const double hw = share * w;
                 X[(2 * c) * S + p] = make_double2(__fma_rn(hw, (double)d0.x, x0.x),
                                                   __fma_rn(hw, (double)d0.y, x0.y));
                 X[(2 * c + 1) * S + p] = make_double2(__fma_rn(hw, (double)d0.x, x1.x),
@@ -2978,8 +3014,9 @@ hipError_t launch_defect(const double2* A, const double2* B, float2* R, const Pl
 }
 
 hipError_t launch_accum(double2* X, const float2* D, double w, const PlaneCoef* P,
-                        long long nxy, long long S, long long N, hipStream_t s) {
-    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, P, nxy, S, N);
+                        double share, long long nxy, long long S, long long N, hipStream_t s) {
+    hipLaunchKernelGGL(k_accum, dim3(grid_1d(N, 256)), dim3(256), 0, s, X, D, w, P, share, nxy,
+                       S, N);
     return hipGetLastError();
 }
 
