@@ -100,6 +100,36 @@ def test_phi0_of_a_plane_source(bc):
     assert abs(rel - ref) <= 1e-12 * ref, (rel, ref)
 
 
+@pytest.mark.parametrize("where", ["first", "last", "first_and_last"])
+def test_phi0_of_sources_at_the_z_walls(where):
+    """The range of planes a source reaches in one iteration, clipped at the
+    z walls: a source only on plane 0, only on the last plane, or on both
+    (the range is then the whole grid)."""
+    _require_gpu()
+    print(f"[residual] source at the z walls: {where}", flush=True)
+    nx, ny, nz = 20, 18, 14
+    pb = inputs.random_problem(nx, ny, nz, seed=47, npml=2)
+    planes = {"first": [0], "last": [nz - 1], "first_and_last": [0, nz - 1]}[where]
+    for key in pb.sources:
+        v = np.zeros_like(pb.sources[key])
+        for k in planes:
+            v[k] = pb.sources[key][k]
+        pb.sources[key] = v
+    s = thiim.Solver(pb, kernel="fused", storage="compact")
+    s.iterate(1)
+    s.stream.synchronize()
+    phi = s.fields().clone()
+    phi0 = _pnorm(phi)
+    assert phi0 > 0
+    s.iterate(1)
+    s.stream.synchronize()
+    ref = _pnorm(s.fields() - phi) / phi0
+    s.set_fields(phi)
+    rel = s.residual()
+    s.close()
+    assert abs(rel - ref) <= 1e-12 * ref, (rel, ref)
+
+
 def test_residual_after_iterations_matches_blocked_and_naive():
     """The same residual from contexts whose iterations run the blocked and
     the naive sweeps: their iterates are bit-identical and the residual pass
