@@ -138,3 +138,31 @@ def test_planted_adjoint_mistake_is_caught(oracle_lib, tmp_path, name):
         assert _dot_gap(pb, 5) > 1e-6, f"planted mistake {name} not detected"
     finally:
         oracle._lib = saved
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 1)])
+def test_transposed_iterates_keep_symmetric_pairs_equal(oracle_lib, bcx, bcy):
+    """The reading behind the pair-equal form of the complex64 transposed
+    sweeps: where the two parts of a split pair have identical coefficients
+    (the z pair everywhere, the x and y pairs off the PML) the transposed
+    iteration gives them identical increments, so from lam = 0 with the
+    adjoint source (which gives both parts of an E component the same value)
+    they stay bitwise equal; on PML planes the x and y pairs of the z-difference
+    components differ."""
+    pb = inputs.random_problem(10, 9, 16, seed=61, npml=3, bcx=bcx, bcy=bcy)
+    coef = oracle.coeffs(pb.eps, pb.sig_e, pb.sig_h, pb.sources, pb.omega, pb.tau, pb.h)
+    x = oracle.zero_fields(pb.eps.shape)
+    oracle.iterate(coef, x, 30, bcx, bcy)
+    w = inputs.rng(5).uniform(0.0, 1.0, pb.eps.shape)
+    g = adjoint.adjoint_source(pb.eps, x, w)
+    lam = np.zeros_like(x)
+    oracle.adjoint_iterate(coef, lam, g, 25, bcx, bcy)
+    for side, sig in ((0, pb.sig_h), (6, pb.sig_e)):  # H parts, E parts
+        pml = sig != 0.0  # planes where the z-difference part has a PML term
+        assert pml.any() and not pml.all()
+        # z pair everywhere
+        assert np.array_equal(lam[side + 4], lam[side + 5])
+        for c in (0, 2):  # x and y pairs
+            a, b = lam[side + c], lam[side + c + 1]
+            assert np.array_equal(a[~pml], b[~pml]), (side, c)
+            assert not np.allclose(a[pml], b[pml]), (side, c)
