@@ -36,14 +36,15 @@ CASES = [((37, 29, 23), (64, 8), 0, "periodic"),
          ((24, 20, 18), (32, 8), 5, "dirichlet")]
 
 
+@pytest.mark.parametrize("storage", ["compact", "full"])
 @pytest.mark.parametrize("shape,tile,zc,bc", CASES)
-def test_residual_matches_fields(shape, tile, zc, bc):
+def test_residual_matches_fields(shape, tile, zc, bc, storage):
     _require_gpu()
-    print(f"[residual] {shape} tile {tile} z chunk {zc} {bc}", flush=True)
+    print(f"[residual] {shape} tile {tile} z chunk {zc} {bc} {storage}", flush=True)
     nz, ny, nx = shape
     d = 1 if bc == "dirichlet" else 0
     pb = inputs.random_problem(nx, ny, nz, seed=41, npml=2, bcx=d, bcy=d)
-    kw = dict(kernel="fused", tile=tile, z_chunk=zc, storage="compact")
+    kw = dict(kernel="fused", tile=tile, z_chunk=zc, storage=storage)
     # Phi(0): one iteration from the state thiim_create leaves
     s0 = thiim.Solver(pb, **kw)
     s0.iterate(1)
@@ -68,19 +69,20 @@ def test_residual_matches_fields(shape, tile, zc, bc):
     assert abs(rel - ref) <= 1e-12 * ref, (rel, ref)
 
 
+@pytest.mark.parametrize("storage", ["compact", "full"])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_phi0_of_a_plane_source(bc):
+def test_phi0_of_a_plane_source(bc, storage):
     """thiim_create forms ||P Phi(0)|| on the planes that a source can reach
     in one iteration (here the plane source and the plane below it) as a grid
     of its own: it must equal the norm over the whole Phi(0)."""
     _require_gpu()
-    print(f"[residual] plane source, bc {bc}", flush=True)
+    print(f"[residual] plane source, bc {bc}, {storage}", flush=True)
     pb = inputs.solar_cell(40, 36, 48, seed=5, npml=6)
     pb.bcx = pb.bcy = bc
     srcs = [v for v in pb.sources.values()]
     planes = sorted({int(k) for v in srcs for k in np.nonzero(np.abs(v).sum(axis=(1, 2)))[0]})
     assert 0 < len(planes) < 4  # a plane source, far from the walls
-    s = thiim.Solver(pb, kernel="fused", storage="compact")
+    s = thiim.Solver(pb, kernel="fused", storage=storage)
     x = torch.zeros((12, 48, 36, 40), dtype=torch.complex128, device="cuda")
     s.set_fields(x)
     s.iterate(1)
