@@ -74,10 +74,14 @@ ALG_BYTES_PER_CELL = {
     # complex64 transposed inner sweep: 12 lam + 16 B record + 12 G read,
     # 12 lam written
     "k_adjoint<64,8,AdjPol32>": 304,
-    # its two-iteration blocked form (per pass), and the instance that also
-    # sums the stored lam into the window accumulator (+ 12 read, 12 written)
-    "k_adjoint32_blocked<32,16,2,false>": 304,
-    "k_adjoint32_blocked<32,16,2,true>": 496,
+    # its two-iteration blocked form (per pass) keeps lam, its source and the
+    # window sum in pair-equal form (a symmetric pair stored once): the bytes
+    # of the forward inner passes, 162 at 512^3 (165 at 128 x 128 x 256, where
+    # the PML planes weigh more), 258 for the instances that also sum into the
+    # window accumulator
+    "k_adjoint32_blocked<32,24,2,false,true>": 162,
+    "k_adjoint32_blocked<32,24,2,true,true>": 258,
+    "k_adjoint32_blocked<32,16,2,false,false>": 162,
     # complex64 inner sweeps (8 B per value) in pair-sum form: per H and E
     # side 3 d + 3 r read and 3 d written where the split pairs are symmetric,
     # 5 of each on the PML planes, + the 16 B record: 160 B off the PML, 162
